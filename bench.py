@@ -1,0 +1,289 @@
+#!/usr/bin/env python3
+"""Benchmark of the offloaded Jacobi hot path on one MI355X.
+
+One step = one ofl_jacobi_run of 100 iterations (sweep, residual, copy-back,
+every nest on the GPU, transfers hoisted) over the 257x257x513 FP32 grid, with
+the inputs already resident in HBM (a data region is open before timing).
+value = lattice updates per second of the whole iteration, in GLUP/s.
+
+Also reported: the sweep kernel against the HBM roofline (HIP-event time of
+every sweep launch inside the timed region), the bfloat16-offset and batched
+forms of the same metric, and the FP64 oracle timed on a bounded sample on the
+host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-variants]
+       [--skip-cpu-baseline] [--profile-only NAME]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GLUP/s + HBM GB/s %peak, 257x257x513 Jacobi: FP32 vs BF16-coef, batched"
+PEAK_HBM_GBS = 8000.0
+OMEGA = np.float32(0.8)
+ITERS = 100
+SHAPE = (257, 257, 513)  # I, J, K
+SWEEP_BYTES = {"f32": 56, "bf16": 32}  # algorithmic bytes per lattice update of the sweep
+ITER_BYTES = {"f32": 72, "bf16": 48}   # sweep + residual + copy-back
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "sweep_f32_257x257x513_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2011_03602_amd", "csrc", "kernels.hip")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def interior(I, J, K):
+    return (I - 2) * (J - 2) * (K - 2)
+
+
+def kernel_hash():
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """Counter-measured HBM bytes per sweep launch, if taken on the current kernel source."""
+    try:
+        with open(PROFILE_TRAFFIC) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def run_single(ofl, arrays, fmt, steps, warmup, tile=None, profile=True):
+    """Time `steps` runs of ITERS iterations on one grid; returns a result dict."""
+    import torch
+
+    g = ofl.Grid(arrays, coef_format=fmt, torch_memory=True)
+    h = g.handle
+    if tile is not None:
+        ofl.ofl_set_tile(h, tile)
+    ofl.ofl_set_offload_mask(h, ofl.OFL_MASK_ALL_GPU, ofl.OFL_XFER_HOISTED)
+    ofl.ofl_data_enter(h)  # inputs resident in HBM before timing
+    for _ in range(warmup):
+        ofl.ofl_jacobi_run(h, ITERS, OMEGA)
+    ofl.ofl_reset_stats(h)
+    ofl.ofl_set_profiling(h, profile)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gosa = None
+    for _ in range(steps):
+        gosa = ofl.ofl_jacobi_run(h, ITERS, OMEGA)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = ofl.ofl_get_stats(h)
+    ofl.ofl_set_profiling(h, False)
+    tile_used = ofl.ofl_get_tile(h).as_dict()
+    ofl.ofl_data_exit(h)
+    g.close()
+    I, J, K = SHAPE
+    lups = interior(I, J, K) * ITERS * steps
+    res = {
+        "seconds": dt,
+        "ms_per_step": 1e3 * dt / steps,
+        "glups": lups / dt / 1e9,
+        "gosa": gosa,
+        "tile": tile_used,
+        "h2d_in_timed_region": int(st.h2d_count),
+        "d2h_in_timed_region": int(st.d2h_count),
+    }
+    if profile:
+        res["nest_ms_avg"] = [st.kernel_ms[n] / max(1, st.timed_nests[n]) for n in range(3)]
+        res["nest_launches"] = [int(st.timed_nests[n]) for n in range(3)]
+    return res
+
+
+def run_batch(ofl, n_grids, fmt, steps, warmup, tune):
+    import torch
+
+    import synth
+
+    log(f"generating {n_grids} uneven grids")
+    probs = synth.make_batch(n_grids)
+    total_lups = sum(interior(*shape) for shape, _ in probs) * ITERS
+    grids = [ofl.Grid(arr, coef_format=fmt) for _, arr in probs]
+    for g in grids:
+        ofl.ofl_data_enter(g.handle)
+    b = ofl.ofl_batch_create([g.handle for g in grids])
+    tuned = None
+    if tune:
+        log("GA tile search for the batch")
+        r = ofl.ofl_batch_tune(b, ofl.ga_params(population=10, generations=6, probe_iters=10, repeats=2))
+        tuned = {"tile": r.best.as_dict(), "probe_ms": r.best_ms, "evaluated": r.evaluated, "rejected": r.rejected}
+    for _ in range(warmup):
+        ofl.ofl_batch_run(b, ITERS, OMEGA, n_grids)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ofl.ofl_batch_run(b, ITERS, OMEGA, n_grids)
+    torch.cuda.synchronize()
+    dt_batch = (time.perf_counter() - t0) / steps
+    tile_used = ofl.ofl_batch_get_tile(b).as_dict()
+    ofl.ofl_batch_destroy(b)
+    # baseline: the same grids one after another, plain single-grid runs
+    for g in grids:
+        ofl.ofl_jacobi_run(g.handle, ITERS, OMEGA)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in grids:
+        ofl.ofl_jacobi_run(g.handle, ITERS, OMEGA)
+    torch.cuda.synchronize()
+    dt_seq = time.perf_counter() - t0
+    for g in grids:
+        ofl.ofl_data_exit(g.handle)
+        g.close()
+    return {
+        "grids": n_grids,
+        "lattice_updates": total_lups,
+        "glups_batched": total_lups / dt_batch / 1e9,
+        "glups_sequential": total_lups / dt_seq / 1e9,
+        "ms_batched": 1e3 * dt_batch,
+        "ms_sequential": 1e3 * dt_seq,
+        "tile": tile_used,
+        "tuner": tuned,
+    }
+
+
+def cpu_baseline(arrays, iters):
+    import oracle
+
+    log(f"oracle: {iters} iterations of 257x257x513 in FP64 on the host")
+    t0 = time.perf_counter()
+    oracle.jacobi(arrays, iters, float(OMEGA))
+    dt = time.perf_counter() - t0
+    I, J, K = SHAPE
+    return {
+        "value": interior(I, J, K) * iters / dt / 1e9,
+        "unit": "GLUP/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"257x257x513 grid, {iters} of the {ITERS} iterations, plain C FP64 oracle, one thread, "
+                  f"{dt:.1f} s including the FP32->FP64 widening of the inputs",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--skip-variants", action="store_true", help="only the FP32 headline")
+    ap.add_argument("--skip-batch", action="store_true")
+    ap.add_argument("--skip-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-grids", type=int, default=64)
+    ap.add_argument("--tune-batch", action="store_true", help="run the GA tile search before the batched run")
+    ap.add_argument("--oracle-iters", type=int, default=10)
+    ap.add_argument("--profile-only", default=None, help="headline|bf16|batch: run just that, no JSON")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2011_03602_amd as ofl
+    import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    ofl.lib()  # fail loudly if the library is missing
+    I, J, K = SHAPE
+    log("generating 257x257x513 inputs")
+    arrays = synth.make_problem(I, J, K)
+
+    if args.profile_only:
+        if args.profile_only == "headline":
+            run_single(ofl, arrays, ofl.OFL_COEF_F32, args.steps, args.warmup, profile=False)
+        elif args.profile_only == "bf16":
+            run_single(ofl, arrays, ofl.OFL_COEF_BF16_OFFSET, args.steps, args.warmup, profile=False)
+        elif args.profile_only == "batch":
+            run_batch(ofl, args.batch_grids, ofl.OFL_COEF_F32, args.steps, args.warmup, False)
+        log("profile run done")
+        return
+
+    log("FP32 headline")
+    head = run_single(ofl, arrays, ofl.OFL_COEF_F32, args.steps, args.warmup)
+    sweep_us = head["nest_ms_avg"][0] * 1e3
+    lup_launch = interior(I, J, K)
+    achieved = SWEEP_BYTES["f32"] * lup_launch / (sweep_us * 1e-6) / 1e9
+    traffic = measured_traffic()
+    roofline = {
+        "bound": "hbm",
+        "kernel": "sweep_kernel (nest S, FP32 coefficients)",
+        "achieved": round(achieved, 1),
+        "peak": PEAK_HBM_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / PEAK_HBM_GBS, 4),
+        "traffic": traffic,
+        "avg_launch_us": round(sweep_us, 2),
+        "algorithmic_bytes_per_launch": SWEEP_BYTES["f32"] * lup_launch,
+        "nest_avg_us": {"sweep": round(sweep_us, 2), "residual": round(head["nest_ms_avg"][1] * 1e3, 2),
+                        "copyback": round(head["nest_ms_avg"][2] * 1e3, 2)},
+    }
+    out = {
+        "metric": METRIC,
+        "value": round(head["glups"], 3),
+        "unit": "GLUP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded SplitMix64 fields)",
+        "config": {
+            "workload": "19-point variable-coefficient Jacobi, 257x257x513 FP32, 100 iterations per step "
+                        "(sweep + residual + copy-back), every nest on the GPU, transfers hoisted, inputs resident",
+            "grid_IJK": list(SHAPE),
+            "iterations_per_step": ITERS,
+            "omega": float(OMEGA),
+            "tile": head["tile"],
+        },
+        "hbm_gbs_iteration": round(head["glups"] * ITER_BYTES["f32"], 1),
+        "roofline": roofline,
+    }
+    if not args.skip_variants:
+        log("bf16-offset variant")
+        bf = run_single(ofl, arrays, ofl.OFL_COEF_BF16_OFFSET, args.steps, args.warmup)
+        bf_sweep_us = bf["nest_ms_avg"][0] * 1e3
+        out["variants"] = {
+            "bf16_offset": {
+                "glups": round(bf["glups"], 3),
+                "ms_per_step": round(bf["ms_per_step"], 3),
+                "hbm_gbs_iteration": round(bf["glups"] * ITER_BYTES["bf16"], 1),
+                "sweep_avg_us": round(bf_sweep_us, 2),
+                "sweep_achieved_gbs": round(SWEEP_BYTES["bf16"] * lup_launch / (bf_sweep_us * 1e-6) / 1e9, 1),
+                "speedup_vs_f32": round(bf["glups"] / head["glups"], 3),
+            }
+        }
+        if not args.skip_batch:
+            log("batched variant")
+            bt = run_batch(ofl, args.batch_grids, ofl.OFL_COEF_F32, max(1, args.steps // 2), 1, args.tune_batch)
+            out["variants"]["batched_f32"] = bt
+    if not args.skip_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(arrays, args.oracle_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,280 @@
+/*
+ * ofl.h -- C ABI of the offloaded Jacobi loop-nest library for MI355X (gfx950).
+ *
+ * The paper's loop-offload method (Sec. 3.2.1, Sec. 4.2.2) takes a CPU
+ * program, gives every parallelisable loop nest one gene bit (1 = run it on
+ * the GPU, 0 = leave it on the CPU), moves variables between host and device
+ * only where a nest on one side reads what the other side wrote, and places
+ * those transfers at the outermost loop level that allows it instead of inside
+ * the inner loops. The program offloaded here is a 3D variable-coefficient
+ * 19-point Jacobi relaxation with three loop nests per iteration:
+ *
+ *   S  sweep      wrk2 = p + omega*ss on the interior, where
+ *                 ss = (a3*s0 - p)*bnd and s0 is the 19-point sum
+ *                   a0 p(i+1) + a1 p(j+1) + a2 p(k+1) + c0 p(i-1) + c1 p(j-1) + c2 p(k-1)
+ *                 + b0 [p(i+1,j+1) - p(i+1,j-1) - p(i-1,j+1) + p(i-1,j-1)]
+ *                 + b1 [p(j+1,k+1) - p(j-1,k+1) - p(j+1,k-1) + p(j-1,k-1)]
+ *                 + b2 [p(i+1,k+1) - p(i-1,k+1) - p(i+1,k-1) + p(i-1,k-1)] + wrk1
+ *                 (every coefficient at the centre point, p the old iterate)
+ *   R  residual   gosa = sum over the interior of ((wrk2 - p)/omega)^2
+ *   C  copy-back  p = wrk2 on the interior
+ *
+ * The interior is {1..I-2} x {1..J-2} x {1..K-2}; the outer one-cell layer of
+ * p is a fixed (Dirichlet) boundary.
+ *
+ * Host array layout: I*J*K floats, linear index i + I*(j + J*k) (i fastest).
+ * Coefficient order everywhere: a0 a1 a2 a3 b0 b1 b2 c0 c1 c2 bnd wrk1.
+ *
+ * Errors: every call returns an OFL_* status. On failure the outputs are left
+ * untouched and ofl_last_error() (per thread) describes the cause. A failing
+ * HIP call makes the handle unusable (OFL_EDEVICE is sticky): after it only
+ * the destroy call is valid. No C++ exception crosses this interface.
+ * Threads: one handle must not be used by two threads at once; separate
+ * handles may run concurrently.
+ */
+#ifndef OFL_H
+#define OFL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define OFL_OK 0
+#define OFL_EINVAL (-1)  /* bad argument */
+#define OFL_ENOMEM (-2)  /* host or device memory exhausted, arena too small */
+#define OFL_EDEVICE (-3) /* a HIP call failed or no GPU is present (sticky) */
+#define OFL_ESTATE (-4)  /* call not valid in the handle's current state */
+#define OFL_ENOTSUP (-5) /* combination not supported */
+
+/* ---- offload gene: one bit per loop nest, 1 = GPU, 0 = CPU (Sec. 3.2.1) --- */
+#define OFL_NEST_SWEEP 1u
+#define OFL_NEST_RESIDUAL 2u
+#define OFL_NEST_COPYBACK 4u
+#define OFL_MASK_ALL_CPU 0u
+#define OFL_MASK_ALL_GPU 7u
+
+/* ---- transfer placement (Sec. 3.2.1, Sec. 4.2.2) ------------------------ */
+/* PER_ITER: every GPU nest copies in all it reads and copies out all it
+ * writes, each time it runs (transfers inside the loop).
+ * HOISTED: an array moves only when the side that needs it does not hold a
+ * valid copy, so read-only arrays move once and nothing moves per iteration
+ * when every nest is on the GPU (transfers at the outermost level). */
+#define OFL_XFER_PER_ITER 0
+#define OFL_XFER_HOISTED 1
+
+/* ---- device storage of the twelve read-only arrays ---------------------- */
+#define OFL_COEF_F32 0          /* FP32 as given */
+#define OFL_COEF_BF16 1         /* bfloat16, round to nearest even */
+#define OFL_COEF_BF16_OFFSET 2  /* per-array FP32 bias + bfloat16 of (x - bias) */
+
+/* ---- residual accumulation ---------------------------------------------- */
+#define OFL_SUM_F64 0       /* squares summed in FP64 */
+#define OFL_SUM_KAHAN_F32 1 /* per-thread compensated (Neumaier) FP32, FP64 across threads */
+
+/* ---- array ids (transfer plans and statistics) -------------------------- */
+enum {
+    OFL_ARR_A0 = 0, OFL_ARR_A1, OFL_ARR_A2, OFL_ARR_A3,
+    OFL_ARR_B0, OFL_ARR_B1, OFL_ARR_B2,
+    OFL_ARR_C0, OFL_ARR_C1, OFL_ARR_C2,
+    OFL_ARR_BND, OFL_ARR_WRK1,
+    OFL_ARR_P = 12, OFL_ARR_WRK2 = 13,
+    OFL_NARRAYS = 14
+};
+
+/* ---- grid description ---------------------------------------------------- */
+typedef struct ofl_grid ofl_grid;
+
+typedef struct ofl_grid_desc {
+    int I, J, K;            /* points per axis, each >= 3; I fastest in memory */
+    int coef_format;        /* OFL_COEF_* */
+    int sum_mode;           /* OFL_SUM_* */
+    float *p;               /* host, I*J*K: initial iterate in, result out */
+    float *wrk2;            /* host, I*J*K: scratch; contents unspecified after a run */
+    const float *coef[12];  /* host, I*J*K each, read-only; order a0..a3 b0..b2 c0..c2 bnd wrk1 */
+    void *stream;           /* hipStream_t to launch on, borrowed; NULL: the library makes one */
+    void *dev_arena;        /* optional caller-owned device memory (e.g. from PyTorch), 256-byte
+                               aligned, at least ofl_grid_device_bytes() bytes; NULL: hipMalloc */
+    size_t dev_arena_bytes; /* size of dev_arena */
+    int device;             /* HIP device ordinal; -1: the device current at creation */
+} ofl_grid_desc;
+
+/* Device bytes a grid of this shape and format needs (arena sizing).
+ * Returns OFL_EINVAL for a dimension below 3 or an unknown format. */
+int ofl_grid_device_bytes(int I, int J, int K, int coef_format, size_t *bytes);
+
+/* Create a grid handle over the caller's host arrays (the CPU program's
+ * variables, Sec. 4.2.2). The host arrays are borrowed and must outlive the
+ * handle; they are read at creation (bfloat16 formats encode the twelve
+ * read-only arrays into library-owned host copies here) and whenever the
+ * transfer plan moves them. Device memory is taken only when a GPU nest first
+ * needs it, so an all-CPU mask runs without a GPU. The initial mask is
+ * OFL_MASK_ALL_GPU with hoisted transfers. EINVAL on a NULL pointer, a
+ * dimension below 3 or an unknown format/sum mode; ENOMEM when host memory
+ * runs out. */
+int ofl_grid_create(const ofl_grid_desc *desc, ofl_grid **out);
+
+/* Release the handle, its device buffers (unless they live in the caller's
+ * arena) and its stream (unless borrowed). NULL is ignored. */
+void ofl_grid_destroy(ofl_grid *g);
+
+/* Choose the device of each loop nest: bit0 sweep, bit1 residual, bit2
+ * copy-back, bit = 1 -> GPU (the gene of Sec. 3.2.1 / Sec. 4.2.2), and the
+ * transfer placement (OFL_XFER_*). Takes effect at the next run; data already
+ * on either side stays valid. EINVAL for bits above 2 or an unknown mode. */
+int ofl_set_offload_mask(ofl_grid *g, unsigned mask, int xfer_mode);
+
+/* Run iters x (S, R, C), each nest on the device its gene bit names, with the
+ * transfers the planner derives (Sec. 4.2.2: a CPU-written variable that the
+ * GPU reads moves host->device; a GPU-written variable the CPU references
+ * moves device->host). On return the caller's p holds the new iterate, unless
+ * a data region is open (ofl_data_enter), in which case p stays on the device
+ * until ofl_update_host/ofl_data_exit. *gosa_out (nullable) receives R of the
+ * last iteration, i.e. the residual of the iterate before the last update;
+ * iters == 0 leaves p alone and gives NaN. EINVAL for iters < 0 or omega == 0
+ * or non-finite; EDEVICE when a GPU nest is requested and no GPU is usable. */
+int ofl_jacobi_run(ofl_grid *g, int iters, float omega, double *gosa_out);
+
+/* Residual of the current iterate without changing it: S with omega = 1 into
+ * wrk2, then R; no copy-back. Uses the devices of the current mask. */
+int ofl_residual(ofl_grid *g, double *gosa_out);
+
+/* Data region (the hoisting of Sec. 3.2.1 across calls, like an OpenACC data
+ * region with "present" inside, Sec. 4.3.1): enter copies to the device every
+ * array the current mask's GPU nests read and keeps the results of later runs
+ * on the device; update_host brings the caller's p (and wrk2 if its last valid
+ * copy is on the device) up to date without leaving; exit does the same and
+ * closes the region. ESTATE when entering twice or exiting when not inside. */
+int ofl_data_enter(ofl_grid *g);
+int ofl_update_host(ofl_grid *g);
+int ofl_data_exit(ofl_grid *g);
+
+/* Per-array FP32 bias of the bfloat16-offset format (zeros for the other
+ * formats), in coefficient order. */
+int ofl_grid_coef_bias(const ofl_grid *g, float bias[12]);
+
+/* ---- kernel tiles ------------------------------------------------------- */
+#define OFL_TILE_NT_LOADS 1   /* non-temporal loads of the coefficient streams */
+#define OFL_TILE_NT_STORES 2  /* non-temporal stores of wrk2 */
+#define OFL_TILE_PREFETCH 4   /* software-pipelined coefficient loads (plane k+1 during k) */
+
+typedef struct ofl_tile {
+    int vec;       /* consecutive i-points per lane: 1, 2 or 4 (a wave spans 64*vec points) */
+    int rows;      /* j-rows per work-group = waves per work-group: 1..8 */
+    int kchunk;    /* k-planes each wave marches through: 1..1024 */
+    int flags;     /* OFL_TILE_* */
+    int occupancy; /* batched launch: resident work-groups per CU (persistent kernels), 1..16;
+                      0 = one work-group per work item */
+} ofl_tile;
+
+/* Set / read the sweep tile of a grid. EINVAL for values outside the ranges. */
+int ofl_set_tile(ofl_grid *g, const ofl_tile *tile);
+int ofl_get_tile(const ofl_grid *g, ofl_tile *tile);
+
+/* ---- statistics ----------------------------------------------------------- */
+typedef struct ofl_stats {
+    uint64_t h2d_count, d2h_count;  /* array transfers issued (scalars excluded) */
+    uint64_t h2d_bytes, d2h_bytes;  /* their payload bytes */
+    uint64_t gpu_nests[3];          /* nest executions on the GPU: S, R, C */
+    uint64_t cpu_nests[3];          /* nest executions on the CPU: S, R, C */
+    double kernel_ms[3];            /* summed GPU time of S, R, C (profiling on) */
+    uint64_t timed_nests[3];        /* executions included in kernel_ms */
+} ofl_stats;
+
+/* Profiling on: each GPU nest is bracketed by HIP events on the grid's stream
+ * and its time is added to kernel_ms at the next synchronisation. */
+int ofl_set_profiling(ofl_grid *g, int on);
+int ofl_get_stats(const ofl_grid *g, ofl_stats *out);
+int ofl_reset_stats(ofl_grid *g);
+
+/* ---- the transfer planner as a pure function ------------------------------ */
+typedef struct ofl_xfer {
+    int iter;   /* iteration index; -1 before the loop (data_enter), iters after it */
+    int nest;   /* 0 S, 1 R, 2 C; -1 outside the nests */
+    int when;   /* 0 before the nest, 1 after it */
+    int array;  /* OFL_ARR_* */
+    int dir;    /* 0 host->device, 1 device->host */
+} ofl_xfer;
+
+/* The transfers ofl_jacobi_run would issue for this mask and mode (Sec. 4.2.2
+ * rules), without touching any data. host_valid/dev_valid (14 entries each,
+ * 0/1, OFL_ARR_* order) give the state before the run and receive the state
+ * after it; sync_host_at_end = 1 models a run outside a data region. Writes at
+ * most cap entries to out (nullable when cap == 0) and the full count to
+ * *count. EINVAL for bad mask/mode/iters; ENOMEM (count still set) when cap is
+ * too small. */
+int ofl_plan(unsigned mask, int xfer_mode, int iters, int sync_host_at_end, uint8_t host_valid[14],
+             uint8_t dev_valid[14], ofl_xfer *out, int cap, int *count);
+
+/* ---- many independent grids in one launch sequence ------------------------- */
+typedef struct ofl_batch ofl_batch;
+
+/* Group n grids (all on one device, one coefficient format and sum mode) for
+ * one batched run: every grid's S, R and C over all iterations run as
+ * batched kernels over a work list of tiles sorted largest grid first,
+ * captured once into a HIP graph and launched as one graph. The grids keep
+ * ownership of their arrays; the batch borrows them and must be destroyed
+ * first. tile may be NULL (defaults). EINVAL for n < 1, NULL grids, mixed
+ * devices or formats. */
+int ofl_batch_create(ofl_grid *const *grids, int n, const ofl_tile *tile, ofl_batch **out);
+void ofl_batch_destroy(ofl_batch *b);
+int ofl_batch_set_tile(ofl_batch *b, const ofl_tile *tile);
+int ofl_batch_get_tile(const ofl_batch *b, ofl_tile *tile);
+
+/* iters x (S, R, C) on the GPU for every grid of the batch, inside the
+ * grids' data regions when open (else the grids' p are copied back at the
+ * end). gosa_out (nullable) receives n residuals, one per grid. The first
+ * call for a given iters/omega captures and instantiates the graph; later
+ * calls replay it. */
+int ofl_batch_run(ofl_batch *b, int iters, float omega, double *gosa_out);
+
+/* ---- genetic-algorithm tile tuner (Sec. 4.2.2 search, over tile genes) ---- */
+typedef struct ofl_ga_params {
+    int population;     /* individuals per generation, >= 2 */
+    int generations;    /* >= 1 */
+    uint64_t seed;      /* random seed of the search */
+    double crossover;   /* single-point crossover probability, 0..1 */
+    double mutation;    /* per-bit mutation probability, 0..1 */
+    int elite;          /* best individuals copied unchanged, >= 0 */
+    int probe_iters;    /* Jacobi iterations per timing run, >= 1 */
+    int repeats;        /* timing runs per individual (median taken), >= 1 */
+    double tolerance;   /* max relative error vs the all-CPU nests on the check grid */
+} ofl_ga_params;
+
+typedef struct ofl_tune_result {
+    ofl_tile best;
+    double best_ms;     /* median time of probe_iters iterations with the best tile */
+    int evaluated;      /* distinct genes measured */
+    int rejected;       /* genes that could not be built or gave wrong results */
+} ofl_tune_result;
+
+/* Search sweep tiles for one grid (or for a batch) with a GA: genes are bit
+ * strings encoding an ofl_tile; a gene whose tile cannot be launched scores
+ * zero, a gene whose result on a small check grid differs from the all-CPU
+ * nests beyond the tolerance gets infinite time (Sec. 4.2.2), the rest are
+ * timed with HIP events; roulette selection on 1/sqrt(time), single-point
+ * crossover, per-bit mutation and elite copy make the next generation. The
+ * best tile is also applied to the grid/batch. p is restored on return. */
+int ofl_grid_tune(ofl_grid *g, const ofl_ga_params *ga, ofl_tune_result *out);
+int ofl_batch_tune(ofl_batch *b, const ofl_ga_params *ga, ofl_tune_result *out);
+
+/* ---- measurement helper ---------------------------------------------------- */
+/* Device-to-device copy of bytes (multiple of 16, 16-byte aligned pointers)
+ * with the library's streaming copy kernel on the given stream (NULL = the
+ * default stream): the practical HBM ceiling the sweep is compared with. */
+int ofl_device_copy(void *dst, const void *src, size_t bytes, void *stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *ofl_last_error(void);
+
+/* Library version string. */
+const char *ofl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OFL_H */

@@ -1,0 +1,341 @@
+// Many independent grids in one launch sequence.
+//
+// Every grid keeps its own arrays; the batch builds device tables (one view
+// per grid plus work lists of tiles) and runs each nest of each iteration as
+// ONE batched kernel over all grids. The whole iteration loop is captured
+// once into a HIP graph and replayed, so a run is a single graph launch.
+// Work lists are sorted largest grid first, so the longest tiles start early
+// and the tail is made of small ones (longest-processing-time order).
+// All three nests run on the GPU here (gene 111) with transfers hoisted out of
+// the loop (paper Sec. 3.2.1): the read-only arrays and p move in before the
+// loop, p moves back after it unless the grid's data region is open.
+#include <algorithm>
+#include <cmath>
+#include <limits>
+#include <memory>
+#include <numeric>
+
+#include "abi_util.hpp"
+#include "batch.hpp"
+
+namespace ofl {
+
+namespace {
+
+constexpr int kRowsPerWaveItem = 16;  // row tiles per wave in one residual/copy-back item
+
+void free_dev(void *&p) {
+    if (p) {
+        (void)hipFree(p);
+        p = nullptr;
+    }
+}
+
+void drop_graph(ofl_batch *b) {
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    b->graph_iters = -1;
+}
+
+void free_tables(ofl_batch *b) {
+    drop_graph(b);
+    free_dev(b->d_views);
+    free_dev(b->d_sitems);
+    free_dev(b->d_ritems);
+    free_dev(b->d_range);
+    free_dev(b->d_partials);
+    b->tables_ready = false;
+}
+
+template <class T>
+void upload(void *&dst, const std::vector<T> &src, hipStream_t s) {
+    free_dev(dst);
+    const size_t bytes = std::max<size_t>(sizeof(T), src.size() * sizeof(T));
+    hip_check(hipMalloc(&dst, bytes), "hipMalloc(batch table)");
+    if (!src.empty())
+        hip_check(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s),
+                  "hipMemcpyAsync(batch table)");
+}
+
+}  // namespace
+
+void batch_build_tables(ofl_batch *b) {
+    if (b->tables_ready)
+        return;
+    free_tables(b);
+    const int n = static_cast<int>(b->grids.size());
+    for (ofl_grid *g : b->grids)
+        grid_ensure_device(g);
+    // Largest grid first.
+    std::vector<int> order(static_cast<size_t>(n));
+    std::iota(order.begin(), order.end(), 0);
+    auto interior = [&](int g) {
+        const ofl_grid *q = b->grids[static_cast<size_t>(g)];
+        return static_cast<long long>(q->I - 2) * (q->J - 2) * (q->K - 2);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return interior(x) > interior(y); });
+
+    const TileCfg &t = b->tile;
+    std::vector<SweepItem> sitems;
+    std::vector<RowItem> ritems;
+    std::vector<int> range(static_cast<size_t>(n) + 1, 0);
+    std::vector<int> count(static_cast<size_t>(n), 0);
+    const int rows_per_item = kRowsPerWaveItem * (kResidualThreads / kWave);
+    for (int g : order) {
+        const ofl_grid *q = b->grids[static_cast<size_t>(g)];
+        const int nti = itiles(q->I, t.vec);
+        const int njb = (q->J - 2 + t.rows - 1) / t.rows;
+        const int nkc = (q->K - 2 + t.kchunk - 1) / t.kchunk;
+        for (int kc = 0; kc < nkc; ++kc)
+            for (int jb = 0; jb < njb; ++jb)
+                for (int it = 0; it < nti; ++it)
+                    sitems.push_back({g, it, jb, kc});
+        const int nrt = nti * (q->J - 2) * (q->K - 2);
+        int slot = 0;
+        for (int first = 0; first < nrt; first += rows_per_item) {
+            ritems.push_back({g, first, std::min(rows_per_item, nrt - first), slot});
+            ++slot;
+        }
+        count[static_cast<size_t>(g)] = slot;
+    }
+    for (int g = 0; g < n; ++g)
+        range[static_cast<size_t>(g) + 1] = range[static_cast<size_t>(g)] + count[static_cast<size_t>(g)];
+    const hipStream_t s = b->stream;
+    hip_check(hipMalloc(&b->d_partials, sizeof(double) * std::max(1, range[static_cast<size_t>(n)])),
+              "hipMalloc(batch partials)");
+    std::vector<GridView> views(static_cast<size_t>(n));
+    for (int g = 0; g < n; ++g) {
+        views[static_cast<size_t>(g)] = b->grids[static_cast<size_t>(g)]->view;
+        views[static_cast<size_t>(g)].partials = static_cast<double *>(b->d_partials) + range[static_cast<size_t>(g)];
+    }
+    upload(b->d_views, views, s);
+    upload(b->d_sitems, sitems, s);
+    upload(b->d_ritems, ritems, s);
+    upload(b->d_range, range, s);
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize(batch tables)");
+    b->n_sitems = static_cast<int>(sitems.size());
+    b->n_ritems = static_cast<int>(ritems.size());
+    b->tables_ready = true;
+}
+
+namespace {
+
+int blocks_for(const ofl_batch *b, int nitems) {
+    if (b->tile.occupancy <= 0)
+        return std::max(1, nitems);
+    return std::max(1, std::min(nitems, b->tile.occupancy * b->cu_count));
+}
+
+}  // namespace
+
+// Enqueue iters x (S, R, finalize, C) for every grid on the batch stream.
+void batch_enqueue(ofl_batch *b, int iters, float omega) {
+    const auto *views = static_cast<const GridView *>(b->d_views);
+    const auto *sitems = static_cast<const SweepItem *>(b->d_sitems);
+    const auto *ritems = static_cast<const RowItem *>(b->d_ritems);
+    const auto *range = static_cast<const int *>(b->d_range);
+    const int n = static_cast<int>(b->grids.size());
+    for (int it = 0; it < iters; ++it) {
+        launch_batch_sweep(views, sitems, b->n_sitems, b->tile, b->fmt != OFL_COEF_F32, omega,
+                           blocks_for(b, b->n_sitems), b->stream);
+        launch_batch_residual(views, ritems, b->n_ritems, b->tile.vec, b->sum_mode, blocks_for(b, b->n_ritems),
+                              b->stream);
+        launch_batch_finalize(views, range, n, omega, b->stream);
+        launch_batch_copyback(views, ritems, b->n_ritems, b->tile.vec, blocks_for(b, b->n_ritems), b->stream);
+    }
+}
+
+void batch_prepare(ofl_batch *b) {
+    // Hoisted transfers before the loop: every grid's inputs to the device.
+    for (ofl_grid *g : b->grids) {
+        grid_ensure_device(g);
+        std::vector<Xfer> xs;
+        plan_enter(OFL_MASK_ALL_GPU, g->valid, xs);
+        grid_exec(g, xs);
+        grid_sync(g);
+    }
+    batch_build_tables(b);
+}
+
+void batch_launch(ofl_batch *b, int iters, float omega) {
+    const bool reuse = b->exec && b->graph_iters == iters && b->graph_omega == omega;
+    if (!reuse) {
+        drop_graph(b);
+        hipGraph_t graph = nullptr;
+        hip_check(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        try {
+            batch_enqueue(b, iters, omega);
+        } catch (...) {
+            (void)hipStreamEndCapture(b->stream, &graph);
+            if (graph)
+                (void)hipGraphDestroy(graph);
+            throw;
+        }
+        hip_check(hipStreamEndCapture(b->stream, &graph), "hipStreamEndCapture");
+        const hipError_t e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        hip_check(e, "hipGraphInstantiate");
+        b->graph_iters = iters;
+        b->graph_omega = omega;
+    }
+    hip_check(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch");
+}
+
+// State after a batched run: p and wrk2 hold their newest values on the device.
+void batch_mark_done(ofl_batch *b, int iters) {
+    for (ofl_grid *g : b->grids) {
+        g->valid.dev[OFL_ARR_P] = 1;
+        g->valid.host[OFL_ARR_P] = 0;
+        g->valid.dev[OFL_ARR_WRK2] = 1;
+        g->valid.host[OFL_ARR_WRK2] = 0;
+        g->gosa_on_dev = true;
+        for (int nest = 0; nest < 3; ++nest)
+            g->stats.gpu_nests[nest] += static_cast<uint64_t>(iters);
+    }
+}
+
+void batch_finish(ofl_batch *b, int iters, double *gosa_out) {
+    hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize(batch)");
+    batch_mark_done(b, iters);
+    for (size_t t = 0; t < b->grids.size(); ++t) {
+        ofl_grid *g = b->grids[t];
+        if (!g->in_region) {
+            std::vector<Xfer> xs;
+            plan_sync_host(iters, g->valid, xs);
+            grid_exec(g, xs);
+        }
+        hip_check(hipMemcpyAsync(&g->gosa_host, g->view.gosa, sizeof(double), hipMemcpyDeviceToHost, g->stream),
+                  "hipMemcpyAsync(gosa)");
+        g->gosa_on_dev = false;
+        g->pending = true;
+        grid_sync(g);
+        if (gosa_out)
+            gosa_out[t] = g->gosa_host;
+    }
+}
+
+void batch_destroy_impl(ofl_batch *b) {
+    if (!b)
+        return;
+    (void)hipSetDevice(b->device);
+    if (b->stream)
+        (void)hipStreamSynchronize(b->stream);
+    free_tables(b);
+    if (b->stream)
+        (void)hipStreamDestroy(b->stream);
+    for (ofl_grid *g : b->grids)
+        g->batch_refs -= 1;
+    delete b;
+}
+
+}  // namespace ofl
+
+using namespace ofl;
+
+extern "C" {
+
+int ofl_batch_create(ofl_grid *const *grids, int n, const ofl_tile *tile, ofl_batch **out) {
+    ofl_batch *made = nullptr;
+    const int rc = guarded(nullptr, [&] {
+        if (!grids || !out || n < 1)
+            fail(OFL_EINVAL, "grids, out and n >= 1 are required");
+        std::string why;
+        if (tile && !tile_valid(*tile, &why))
+            fail(OFL_EINVAL, why);
+        for (int t = 0; t < n; ++t) {
+            if (!grids[t])
+                fail(OFL_EINVAL, "a grid handle is NULL");
+            if (grids[t]->broken)
+                fail(OFL_EDEVICE, "a grid handle is unusable after a device error");
+            if (grids[t]->fmt != grids[0]->fmt || grids[t]->sum_mode != grids[0]->sum_mode)
+                fail(OFL_EINVAL, "all grids of a batch need one coefficient format and sum mode");
+            for (int u = 0; u < t; ++u)
+                if (grids[u] == grids[t])
+                    fail(OFL_EINVAL, "a grid appears twice in the batch");
+        }
+        std::unique_ptr<ofl_batch> b(new ofl_batch);
+        b->grids.assign(grids, grids + n);
+        b->fmt = grids[0]->fmt;
+        b->sum_mode = grids[0]->sum_mode;
+        if (tile) {
+            b->tile = to_cfg(*tile);
+        } else {
+            b->tile.vec = 2;
+            b->tile.rows = 4;
+            b->tile.kchunk = 32;
+            b->tile.flags = 0;
+            b->tile.occupancy = 0;
+        }
+        for (ofl_grid *g : b->grids)
+            grid_ensure_device(g);
+        b->device = grids[0]->device;
+        for (ofl_grid *g : b->grids)
+            if (g->device != b->device)
+                fail(OFL_EINVAL, "all grids of a batch must live on one device");
+        hip_check(hipSetDevice(b->device), "hipSetDevice");
+        hip_check(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking), "hipStreamCreate(batch)");
+        b->cu_count = device_cu_count(b->device);
+        for (ofl_grid *g : b->grids)
+            g->batch_refs += 1;
+        made = b.release();
+    });
+    if (rc == OFL_OK)
+        *out = made;
+    return rc;
+}
+
+void ofl_batch_destroy(ofl_batch *b) { batch_destroy_impl(b); }
+
+int ofl_batch_set_tile(ofl_batch *b, const ofl_tile *tile) {
+    return guarded(nullptr, [&] {
+        if (!b || !tile)
+            fail(OFL_EINVAL, "NULL argument");
+        std::string why;
+        if (!tile_valid(*tile, &why))
+            fail(OFL_EINVAL, why);
+        const TileCfg c = to_cfg(*tile);
+        if (c.vec != b->tile.vec || c.rows != b->tile.rows || c.kchunk != b->tile.kchunk ||
+            c.flags != b->tile.flags || c.occupancy != b->tile.occupancy) {
+            hip_check(hipSetDevice(b->device), "hipSetDevice");
+            hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+            free_tables(b);
+            b->tile = c;
+        }
+    });
+}
+
+int ofl_batch_get_tile(const ofl_batch *b, ofl_tile *tile) {
+    return guarded(nullptr, [&] {
+        if (!b || !tile)
+            fail(OFL_EINVAL, "NULL argument");
+        *tile = to_tile(b->tile);
+    });
+}
+
+int ofl_batch_run(ofl_batch *b, int iters, float omega, double *gosa_out) {
+    return guarded(nullptr, [&] {
+        if (!b)
+            fail(OFL_EINVAL, "NULL batch handle");
+        if (iters < 0)
+            fail(OFL_EINVAL, "iters must be >= 0");
+        if (!std::isfinite(omega) || omega == 0.f)
+            fail(OFL_EINVAL, "omega must be finite and non-zero");
+        for (ofl_grid *g : b->grids)
+            if (g->broken)
+                fail(OFL_EDEVICE, "a grid of the batch is unusable after a device error");
+        if (iters == 0) {
+            if (gosa_out)
+                for (size_t t = 0; t < b->grids.size(); ++t)
+                    gosa_out[t] = std::numeric_limits<double>::quiet_NaN();
+            return;
+        }
+        hip_check(hipSetDevice(b->device), "hipSetDevice");
+        batch_prepare(b);
+        batch_launch(b, iters, omega);
+        batch_finish(b, iters, gosa_out);
+    });
+}
+
+}  // extern "C"

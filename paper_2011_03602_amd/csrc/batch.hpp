@@ -1,0 +1,41 @@
+// Batch handle: several grids run by batched kernels in one HIP graph.
+#pragma once
+
+#include <cmath>
+#include <vector>
+
+#include "grid.hpp"
+
+struct ofl_batch {
+    std::vector<ofl_grid *> grids;
+    int fmt = OFL_COEF_F32;
+    int sum_mode = OFL_SUM_F64;
+    int device = 0;
+    int cu_count = 256;
+    hipStream_t stream = nullptr;
+    ofl::TileCfg tile;
+
+    bool tables_ready = false;
+    void *d_views = nullptr;
+    void *d_sitems = nullptr;
+    void *d_ritems = nullptr;
+    void *d_range = nullptr;
+    void *d_partials = nullptr;
+    int n_sitems = 0;
+    int n_ritems = 0;
+
+    hipGraphExec_t exec = nullptr;
+    int graph_iters = -1;
+    float graph_omega = NAN;
+};
+
+namespace ofl {
+
+void batch_build_tables(ofl_batch *b);
+void batch_prepare(ofl_batch *b);
+void batch_enqueue(ofl_batch *b, int iters, float omega);
+void batch_launch(ofl_batch *b, int iters, float omega);
+void batch_finish(ofl_batch *b, int iters, double *gosa_out);
+void batch_mark_done(ofl_batch *b, int iters);
+
+}  // namespace ofl

@@ -1,0 +1,642 @@
+// Grid handle, transfer execution, the iteration driver and the grid part of
+// the C interface.
+//
+// The iteration driver is the offloaded program's outer loop (paper Sec.
+// 3.2.1): for every iteration it runs the sweep, residual and copy-back nests,
+// each on the side its gene bit names, and before/after each nest issues the
+// transfers the planner derives from the variable reference relations (Sec.
+// 4.2.2).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <memory>
+
+#include "abi_util.hpp"
+#include "cpu_nests.hpp"
+#include "grid.hpp"
+
+namespace ofl {
+
+namespace {
+
+thread_local std::string t_last_error;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+void set_last_error(const std::string &msg) { t_last_error = msg; }
+
+void fail(int code, const std::string &msg) { throw Error(code, msg); }
+
+void hip_check(hipError_t e, const char *what) {
+    if (e != hipSuccess)
+        throw Error(OFL_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+Layout make_layout(int I, int J, int K, int coef_format) {
+    Layout L;
+    L.I = I;
+    L.J = J;
+    L.K = K;
+    L.pitch = round_up(I, kPitchAlign);
+    L.plane = static_cast<size_t>(L.pitch) * J;
+    L.elems = L.plane * K;
+    L.coef_elem = coef_format == OFL_COEF_F32 ? 4 : 2;
+    size_t off = 0;
+    auto place = [&](size_t eb) {
+        off = align_up(off + kGuard * eb, 256);
+        const size_t at = off;
+        off += (L.elems + kGuard) * eb;
+        return at;
+    };
+    for (int a = 0; a < kNCoef; ++a)
+        L.off[a] = place(L.coef_elem);
+    L.off[OFL_ARR_P] = place(4);
+    L.off[OFL_ARR_WRK2] = place(4);
+    L.staging_off = align_up(off, 256);
+    off = L.staging_off + static_cast<size_t>(I) * J * K * 4;
+    L.partials_off = align_up(off, 256);
+    off = L.partials_off + sizeof(double) * kResidualBlocks;
+    L.gosa_off = align_up(off, 256);
+    off = L.gosa_off + 256;
+    L.total = align_up(off, 4096);
+    return L;
+}
+
+bool tile_valid(const ofl_tile &t, std::string *why) {
+    auto bad = [&](const char *m) {
+        if (why)
+            *why = m;
+        return false;
+    };
+    if (t.vec != 1 && t.vec != 2 && t.vec != 4)
+        return bad("tile.vec must be 1, 2 or 4");
+    if (t.rows < 1 || t.rows > 8)
+        return bad("tile.rows must be in 1..8");
+    if (t.kchunk < 1 || t.kchunk > 1024)
+        return bad("tile.kchunk must be in 1..1024");
+    if (t.flags < 0 || t.flags > 7)
+        return bad("tile.flags has unknown bits");
+    if (t.occupancy < 0 || t.occupancy > 16)
+        return bad("tile.occupancy must be in 0..16");
+    return true;
+}
+
+TileCfg to_cfg(const ofl_tile &t) {
+    TileCfg c;
+    c.vec = t.vec;
+    c.rows = t.rows;
+    c.kchunk = t.kchunk;
+    c.flags = t.flags;
+    c.occupancy = t.occupancy;
+    return c;
+}
+
+ofl_tile to_tile(const TileCfg &c) {
+    ofl_tile t;
+    t.vec = c.vec;
+    t.rows = c.rows;
+    t.kchunk = c.kchunk;
+    t.flags = c.flags;
+    t.occupancy = c.occupancy;
+    return t;
+}
+
+TileCfg default_tile(int I) {
+    TileCfg t;
+    const int interior = I - 2;
+    t.vec = interior > 128 ? 4 : (interior > 64 ? 2 : 1);
+    t.rows = 4;
+    t.kchunk = 32;
+    t.flags = 0;
+    t.occupancy = 0;
+    return t;
+}
+
+void *grid_array_ptr(ofl_grid *g, int a) { return g->block + g->lay.off[a]; }
+
+void grid_ensure_device(ofl_grid *g) {
+    if (g->dev_ready) {
+        hip_check(hipSetDevice(g->device), "hipSetDevice");
+        return;
+    }
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1)
+        fail(OFL_EDEVICE, "a GPU nest was requested but no HIP device is available");
+    int dev = g->want_device;
+    if (dev < 0)
+        hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (dev >= count)
+        fail(OFL_EINVAL, "desc.device is not a valid HIP device ordinal");
+    hip_check(hipSetDevice(dev), "hipSetDevice");
+    g->device = dev;
+    g->lay = make_layout(g->I, g->J, g->K, g->fmt);
+    if (g->arena) {
+        if (g->arena_bytes < g->lay.total)
+            fail(OFL_ENOMEM, "dev_arena is smaller than ofl_grid_device_bytes()");
+        g->block = static_cast<char *>(g->arena);
+        g->own_block = false;
+    } else {
+        void *ptr = nullptr;
+        const hipError_t e = hipMalloc(&ptr, g->lay.total);
+        if (e != hipSuccess)
+            fail(OFL_ENOMEM, std::string("hipMalloc of the grid's device block failed: ") + hipGetErrorString(e));
+        g->block = static_cast<char *>(ptr);
+        g->own_block = true;
+    }
+    if (g->user_stream) {
+        g->stream = static_cast<hipStream_t>(g->user_stream);
+        g->own_stream = false;
+    } else {
+        hip_check(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking), "hipStreamCreate");
+        g->own_stream = true;
+    }
+    // Zero the whole block once (guards and padding included) so that every
+    // value a wave may read past a row end is defined.
+    launch_fill_zero(g->block, g->lay.total, g->stream);
+    GridView &v = g->view;
+    v.p = reinterpret_cast<float *>(g->block + g->lay.off[OFL_ARR_P]);
+    v.wrk2 = reinterpret_cast<float *>(g->block + g->lay.off[OFL_ARR_WRK2]);
+    for (int a = 0; a < kNCoef; ++a) {
+        v.coef[a] = g->block + g->lay.off[a];
+        v.bias[a] = g->bias[a];
+    }
+    v.I = g->I;
+    v.J = g->J;
+    v.K = g->K;
+    v.pitch = g->lay.pitch;
+    v.plane = static_cast<long long>(g->lay.plane);
+    v.partials = reinterpret_cast<double *>(g->block + g->lay.partials_off);
+    v.gosa = reinterpret_cast<double *>(g->block + g->lay.gosa_off);
+    g->dev_ready = true;
+    g->pending = true;
+}
+
+namespace {
+
+size_t array_elem_bytes(const ofl_grid *g, int a) { return (a < kNCoef && g->fmt != OFL_COEF_F32) ? 2 : 4; }
+
+const void *host_src(const ofl_grid *g, int a) {
+    if (a < kNCoef)
+        return g->fmt == OFL_COEF_F32 ? static_cast<const void *>(g->coef[a])
+                                       : static_cast<const void *>(g->enc[a].data());
+    return a == OFL_ARR_P ? g->p : g->wrk2;
+}
+
+void harvest_events(ofl_grid *g) {
+    for (size_t t = 0; t < g->ev_used; ++t) {
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, g->ev[2 * t], g->ev[2 * t + 1]), "hipEventElapsedTime");
+        const int nest = g->ev_nest[t];
+        g->stats.kernel_ms[nest] += ms;
+        g->stats.timed_nests[nest] += 1;
+    }
+    g->ev_used = 0;
+}
+
+void prof_begin(ofl_grid *g, int nest) {
+    if (!g->profiling)
+        return;
+    if (g->ev.size() < 2 * (g->ev_used + 1)) {
+        for (int t = 0; t < 2; ++t) {
+            hipEvent_t e;
+            hip_check(hipEventCreate(&e), "hipEventCreate");
+            g->ev.push_back(e);
+        }
+        g->ev_nest.push_back(0);
+    }
+    g->ev_nest[g->ev_used] = nest;
+    hip_check(hipEventRecord(g->ev[2 * g->ev_used], g->stream), "hipEventRecord");
+}
+
+void prof_end(ofl_grid *g) {
+    if (!g->profiling)
+        return;
+    hip_check(hipEventRecord(g->ev[2 * g->ev_used + 1], g->stream), "hipEventRecord");
+    g->ev_used += 1;
+}
+
+void gpu_nest(ofl_grid *g, int nest, float omega) {
+    prof_begin(g, nest);
+    if (nest == kS) {
+        launch_sweep(g->view, g->tile, g->fmt != OFL_COEF_F32, omega, g->stream);
+    } else if (nest == kR) {
+        launch_residual(g->view, g->tile.vec, g->sum_mode, omega, g->stream);
+        g->gosa_on_dev = true;
+    } else {
+        launch_copyback(g->view, g->tile.vec, g->stream);
+    }
+    prof_end(g);
+    g->stats.gpu_nests[nest] += 1;
+    g->pending = true;
+}
+
+void cpu_nest(ofl_grid *g, int nest, float omega) {
+    if (g->pending)
+        grid_sync(g);
+    if (nest == kS) {
+        if (g->fmt == OFL_COEF_F32) {
+            cpu_sweep_f32(g->I, g->J, g->K, g->coef, g->p, g->wrk2, omega);
+        } else {
+            const uint16_t *enc[kNCoef];
+            for (int a = 0; a < kNCoef; ++a)
+                enc[a] = g->enc[a].data();
+            cpu_sweep_bf16(g->I, g->J, g->K, enc, g->bias, g->p, g->wrk2, omega);
+        }
+    } else if (nest == kR) {
+        g->gosa_host = cpu_residual(g->I, g->J, g->K, g->p, g->wrk2, omega);
+        g->gosa_on_dev = false;
+    } else {
+        cpu_copyback(g->I, g->J, g->K, g->wrk2, g->p);
+    }
+    g->stats.cpu_nests[nest] += 1;
+}
+
+}  // namespace
+
+// The outer loop of the offloaded program: iters x (S, R[, C]).
+void grid_run_loop(ofl_grid *g, int iters, float omega, int nests) {
+    std::vector<Xfer> xs;
+    for (int it = 0; it < iters; ++it) {
+        for (int nest = 0; nest < nests; ++nest) {
+            const bool gpu = ((g->mask >> nest) & 1u) != 0;
+            if (gpu)
+                grid_ensure_device(g);
+            xs.clear();
+            plan_before(it, nest, gpu, g->mode, g->valid, xs);
+            grid_exec(g, xs);
+            if (gpu)
+                gpu_nest(g, nest, omega);
+            else
+                cpu_nest(g, nest, omega);
+            xs.clear();
+            plan_after(it, nest, gpu, g->mode, g->valid, xs);
+            grid_exec(g, xs);
+            if (gpu && nest == kR && g->mode == OFL_XFER_PER_ITER) {
+                // per-iteration placement: the residual scalar comes back every time
+                hip_check(hipMemcpyAsync(&g->gosa_host, g->view.gosa, sizeof(double), hipMemcpyDeviceToHost,
+                                         g->stream),
+                          "hipMemcpyAsync(gosa)");
+                g->gosa_on_dev = false;
+            }
+        }
+    }
+}
+
+double grid_fetch_gosa(ofl_grid *g) {
+    if (g->gosa_on_dev) {
+        hip_check(hipMemcpyAsync(&g->gosa_host, g->view.gosa, sizeof(double), hipMemcpyDeviceToHost, g->stream),
+                  "hipMemcpyAsync(gosa)");
+        g->gosa_on_dev = false;
+        g->pending = true;
+    }
+    grid_sync(g);
+    return g->gosa_host;
+}
+
+namespace {
+
+void encode_bf16(ofl_grid *g) {
+    for (int a = 0; a < kNCoef; ++a) {
+        const float *x = g->coef[a];
+        const size_t n = g->n;
+        float lo = std::numeric_limits<float>::infinity();
+        float hi = -lo;
+        bool exact = true;
+        for (size_t t = 0; t < n; ++t) {
+            const float v = x[t];
+            lo = std::min(lo, v);
+            hi = std::max(hi, v);
+            uint32_t u;
+            std::memcpy(&u, &v, sizeof u);
+            if ((u & 0xffffu) != 0)
+                exact = false;
+        }
+        float b = 0.f;
+        if (g->fmt == OFL_COEF_BF16_OFFSET && !exact)
+            b = static_cast<float>(0.5 * (static_cast<double>(lo) + static_cast<double>(hi)));
+        g->bias[a] = b;
+        g->enc[a].resize(n);
+        cpu_encode_bf16(x, n, b, g->enc[a].data());
+    }
+}
+
+template <class F>
+int grid_call(ofl_grid *g, F &&f) {
+    if (!g) {
+        set_last_error("NULL grid handle");
+        return OFL_EINVAL;
+    }
+    if (g->broken) {
+        set_last_error("grid handle unusable after an earlier device error");
+        return OFL_EDEVICE;
+    }
+    bool dev_err = false;
+    const int rc = guarded(&dev_err, f);
+    if (dev_err && g->dev_ready)
+        g->broken = true;
+    return rc;
+}
+
+}  // namespace
+
+void grid_sync(ofl_grid *g) {
+    if (!g->dev_ready)
+        return;
+    hip_check(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+    harvest_events(g);
+    g->pending = false;
+}
+
+void grid_exec(ofl_grid *g, const std::vector<Xfer> &xs) {
+    for (const Xfer &x : xs) {
+        grid_ensure_device(g);
+        const size_t eb = array_elem_bytes(g, x.array);
+        const size_t bytes = g->n * eb;
+        void *staging = g->block + g->lay.staging_off;
+        void *arr = grid_array_ptr(g, x.array);
+        if (x.dir == 0) {
+            hip_check(hipMemcpyAsync(staging, host_src(g, x.array), bytes, hipMemcpyHostToDevice, g->stream),
+                      "hipMemcpyAsync(host->device)");
+            launch_pack(staging, arr, g->I, g->J, g->K, g->lay.pitch, static_cast<int>(eb), g->stream);
+            g->stats.h2d_count += 1;
+            g->stats.h2d_bytes += bytes;
+        } else {
+            void *dst = x.array == OFL_ARR_P ? static_cast<void *>(g->p) : static_cast<void *>(g->wrk2);
+            launch_unpack(arr, staging, g->I, g->J, g->K, g->lay.pitch, static_cast<int>(eb), g->stream);
+            hip_check(hipMemcpyAsync(dst, staging, bytes, hipMemcpyDeviceToHost, g->stream),
+                      "hipMemcpyAsync(device->host)");
+            g->stats.d2h_count += 1;
+            g->stats.d2h_bytes += bytes;
+        }
+        g->pending = true;
+    }
+}
+
+}  // namespace ofl
+
+using namespace ofl;
+
+extern "C" {
+
+const char *ofl_last_error(void) { return t_last_error.c_str(); }
+
+const char *ofl_version(void) { return "ofl 0.1.0 (gfx950)"; }
+
+int ofl_grid_device_bytes(int I, int J, int K, int coef_format, size_t *bytes) {
+    return guarded(nullptr, [&] {
+        if (!bytes)
+            fail(OFL_EINVAL, "bytes is NULL");
+        if (I < 3 || J < 3 || K < 3)
+            fail(OFL_EINVAL, "every grid dimension must be >= 3");
+        if (coef_format < OFL_COEF_F32 || coef_format > OFL_COEF_BF16_OFFSET)
+            fail(OFL_EINVAL, "unknown coef_format");
+        *bytes = make_layout(I, J, K, coef_format).total;
+    });
+}
+
+int ofl_grid_create(const ofl_grid_desc *d, ofl_grid **out) {
+    return guarded(nullptr, [&] {
+        if (!d || !out)
+            fail(OFL_EINVAL, "desc and out must not be NULL");
+        if (d->I < 3 || d->J < 3 || d->K < 3)
+            fail(OFL_EINVAL, "every grid dimension must be >= 3");
+        const long long n = static_cast<long long>(d->I) * d->J * d->K;
+        if (n > (1LL << 36) || static_cast<long long>(round_up(d->I, kPitchAlign)) * d->J * d->K > (1LL << 40))
+            fail(OFL_EINVAL, "grid too large");
+        if (static_cast<long long>(d->J) * d->K > 0x7fffffffLL / 4)
+            fail(OFL_EINVAL, "grid has too many rows");
+        if (d->coef_format < OFL_COEF_F32 || d->coef_format > OFL_COEF_BF16_OFFSET)
+            fail(OFL_EINVAL, "unknown coef_format");
+        if (d->sum_mode != OFL_SUM_F64 && d->sum_mode != OFL_SUM_KAHAN_F32)
+            fail(OFL_EINVAL, "unknown sum_mode");
+        if (!d->p || !d->wrk2)
+            fail(OFL_EINVAL, "p and wrk2 must not be NULL");
+        for (int a = 0; a < kNCoef; ++a)
+            if (!d->coef[a])
+                fail(OFL_EINVAL, "every coefficient array must be given");
+        if (d->dev_arena && (reinterpret_cast<uintptr_t>(d->dev_arena) % 256) != 0)
+            fail(OFL_EINVAL, "dev_arena must be 256-byte aligned");
+        std::unique_ptr<ofl_grid> g(new ofl_grid);
+        g->I = d->I;
+        g->J = d->J;
+        g->K = d->K;
+        g->n = static_cast<size_t>(n);
+        g->fmt = d->coef_format;
+        g->sum_mode = d->sum_mode;
+        g->p = d->p;
+        g->wrk2 = d->wrk2;
+        for (int a = 0; a < kNCoef; ++a)
+            g->coef[a] = d->coef[a];
+        g->user_stream = d->stream;
+        g->arena = d->dev_arena;
+        g->arena_bytes = d->dev_arena_bytes;
+        g->want_device = d->device;
+        g->tile = default_tile(d->I);
+        if (g->fmt != OFL_COEF_F32)
+            encode_bf16(g.get());
+        *out = g.release();
+    });
+}
+
+void ofl_grid_destroy(ofl_grid *g) {
+    if (!g)
+        return;
+    if (g->dev_ready) {
+        (void)hipSetDevice(g->device);
+        (void)hipStreamSynchronize(g->stream);
+        for (hipEvent_t e : g->ev)
+            (void)hipEventDestroy(e);
+        if (g->own_block)
+            (void)hipFree(g->block);
+        if (g->own_stream)
+            (void)hipStreamDestroy(g->stream);
+    }
+    delete g;
+}
+
+int ofl_set_offload_mask(ofl_grid *g, unsigned mask, int xfer_mode) {
+    return grid_call(g, [&] {
+        if (mask > OFL_MASK_ALL_GPU)
+            fail(OFL_EINVAL, "mask has bits above bit 2");
+        if (xfer_mode != OFL_XFER_PER_ITER && xfer_mode != OFL_XFER_HOISTED)
+            fail(OFL_EINVAL, "unknown xfer_mode");
+        g->mask = mask;
+        g->mode = xfer_mode;
+    });
+}
+
+int ofl_jacobi_run(ofl_grid *g, int iters, float omega, double *gosa_out) {
+    return grid_call(g, [&] {
+        if (iters < 0)
+            fail(OFL_EINVAL, "iters must be >= 0");
+        if (!std::isfinite(omega) || omega == 0.f)
+            fail(OFL_EINVAL, "omega must be finite and non-zero");
+        if (g->batch_refs > 0 && g->mask != OFL_MASK_ALL_GPU)
+            fail(OFL_ESTATE, "a grid inside a batch runs with every nest on the GPU");
+        if (iters == 0) {
+            if (gosa_out)
+                *gosa_out = std::numeric_limits<double>::quiet_NaN();
+            return;
+        }
+        grid_run_loop(g, iters, omega, 3);
+        if (!g->in_region) {
+            std::vector<Xfer> xs;
+            plan_sync_host(iters, g->valid, xs);
+            grid_exec(g, xs);
+        }
+        const double gosa = grid_fetch_gosa(g);
+        if (gosa_out)
+            *gosa_out = gosa;
+    });
+}
+
+int ofl_residual(ofl_grid *g, double *gosa_out) {
+    return grid_call(g, [&] {
+        if (!gosa_out)
+            fail(OFL_EINVAL, "gosa_out must not be NULL");
+        grid_run_loop(g, 1, 1.0f, 2);
+        *gosa_out = grid_fetch_gosa(g);
+    });
+}
+
+int ofl_data_enter(ofl_grid *g) {
+    return grid_call(g, [&] {
+        if (g->in_region)
+            fail(OFL_ESTATE, "data region already open");
+        if (g->mask != 0) {
+            grid_ensure_device(g);
+            std::vector<Xfer> xs;
+            plan_enter(g->mask, g->valid, xs);
+            grid_exec(g, xs);
+            grid_sync(g);
+        }
+        g->in_region = true;
+    });
+}
+
+int ofl_update_host(ofl_grid *g) {
+    return grid_call(g, [&] {
+        std::vector<Xfer> xs;
+        plan_sync_host(-1, g->valid, xs);
+        grid_exec(g, xs);
+        grid_sync(g);
+    });
+}
+
+int ofl_data_exit(ofl_grid *g) {
+    return grid_call(g, [&] {
+        if (!g->in_region)
+            fail(OFL_ESTATE, "no data region is open");
+        std::vector<Xfer> xs;
+        plan_sync_host(-1, g->valid, xs);
+        grid_exec(g, xs);
+        grid_sync(g);
+        g->in_region = false;
+    });
+}
+
+int ofl_grid_coef_bias(const ofl_grid *g, float bias[12]) {
+    return guarded(nullptr, [&] {
+        if (!g || !bias)
+            fail(OFL_EINVAL, "NULL argument");
+        for (int a = 0; a < kNCoef; ++a)
+            bias[a] = g->bias[a];
+    });
+}
+
+int ofl_set_tile(ofl_grid *g, const ofl_tile *tile) {
+    return grid_call(g, [&] {
+        std::string why;
+        if (!tile)
+            fail(OFL_EINVAL, "tile is NULL");
+        if (!tile_valid(*tile, &why))
+            fail(OFL_EINVAL, why);
+        g->tile = to_cfg(*tile);
+    });
+}
+
+int ofl_get_tile(const ofl_grid *g, ofl_tile *tile) {
+    return guarded(nullptr, [&] {
+        if (!g || !tile)
+            fail(OFL_EINVAL, "NULL argument");
+        *tile = to_tile(g->tile);
+    });
+}
+
+int ofl_set_profiling(ofl_grid *g, int on) {
+    return grid_call(g, [&] {
+        if (g->dev_ready)
+            grid_sync(g);
+        g->profiling = on != 0;
+    });
+}
+
+int ofl_get_stats(const ofl_grid *g, ofl_stats *out) {
+    return guarded(nullptr, [&] {
+        if (!g || !out)
+            fail(OFL_EINVAL, "NULL argument");
+        *out = g->stats;
+    });
+}
+
+int ofl_reset_stats(ofl_grid *g) {
+    return grid_call(g, [&] {
+        if (g->dev_ready)
+            grid_sync(g);
+        g->stats = ofl_stats{};
+    });
+}
+
+int ofl_plan(unsigned mask, int xfer_mode, int iters, int sync_host_at_end, uint8_t host_valid[14],
+             uint8_t dev_valid[14], ofl_xfer *out, int cap, int *count) {
+    return guarded(nullptr, [&] {
+        if (mask > OFL_MASK_ALL_GPU)
+            fail(OFL_EINVAL, "mask has bits above bit 2");
+        if (xfer_mode != OFL_XFER_PER_ITER && xfer_mode != OFL_XFER_HOISTED)
+            fail(OFL_EINVAL, "unknown xfer_mode");
+        if (iters < 0 || !host_valid || !dev_valid || !count || cap < 0 || (cap > 0 && !out))
+            fail(OFL_EINVAL, "bad iters, state or output arguments");
+        Validity v;
+        for (int a = 0; a < OFL_NARRAYS; ++a) {
+            v.host[a] = host_valid[a] ? 1 : 0;
+            v.dev[a] = dev_valid[a] ? 1 : 0;
+            if (!v.host[a] && !v.dev[a])
+                fail(OFL_EINVAL, "an array is valid on neither side");
+        }
+        std::vector<Xfer> xs;
+        for (int it = 0; it < iters; ++it)
+            for (int nest = 0; nest < 3; ++nest) {
+                const bool gpu = ((mask >> nest) & 1u) != 0;
+                plan_before(it, nest, gpu, xfer_mode, v, xs);
+                plan_after(it, nest, gpu, xfer_mode, v, xs);
+            }
+        if (sync_host_at_end && iters > 0)
+            plan_sync_host(iters, v, xs);
+        *count = static_cast<int>(xs.size());
+        for (int a = 0; a < OFL_NARRAYS; ++a) {
+            host_valid[a] = v.host[a];
+            dev_valid[a] = v.dev[a];
+        }
+        const int m = std::min(cap, static_cast<int>(xs.size()));
+        for (int t = 0; t < m; ++t)
+            out[t] = ofl_xfer{xs[t].iter, xs[t].nest, xs[t].when, xs[t].array, xs[t].dir};
+        if (static_cast<int>(xs.size()) > cap)
+            fail(OFL_ENOMEM, "out has fewer entries than the plan");
+    });
+}
+
+int ofl_device_copy(void *dst, const void *src, size_t bytes, void *stream) {
+    return guarded(nullptr, [&] {
+        if (!dst || !src)
+            fail(OFL_EINVAL, "NULL pointer");
+        if (bytes % 16 != 0 || reinterpret_cast<uintptr_t>(dst) % 16 != 0 ||
+            reinterpret_cast<uintptr_t>(src) % 16 != 0)
+            fail(OFL_EINVAL, "bytes and both pointers must be multiples of 16");
+        launch_copy(dst, src, bytes, static_cast<hipStream_t>(stream));
+    });
+}
+
+}  // extern "C"

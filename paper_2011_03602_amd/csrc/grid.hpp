@@ -1,0 +1,70 @@
+// The grid handle: the CPU program's variables (borrowed host arrays), their
+// device copies, the offload gene and the validity state the planner works on.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "ofl_internal.hpp"
+#include "planner.hpp"
+
+struct ofl_grid {
+    int I = 0, J = 0, K = 0;
+    size_t n = 0;  // I*J*K
+    int fmt = OFL_COEF_F32;
+    int sum_mode = OFL_SUM_F64;
+    float *p = nullptr;
+    float *wrk2 = nullptr;
+    const float *coef[ofl::kNCoef] = {};
+    void *user_stream = nullptr;
+    void *arena = nullptr;
+    size_t arena_bytes = 0;
+    int want_device = -1;
+
+    unsigned mask = OFL_MASK_ALL_GPU;
+    int mode = OFL_XFER_HOISTED;
+    ofl::TileCfg tile;
+    bool in_region = false;
+    ofl::Validity valid = ofl::fresh_validity();
+
+    // bfloat16 formats: encoded host copies of the read-only arrays + biases
+    std::vector<uint16_t> enc[ofl::kNCoef];
+    float bias[ofl::kNCoef] = {};
+
+    // device side (created on first GPU use)
+    bool dev_ready = false;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char *block = nullptr;
+    bool own_block = false;
+    ofl::Layout lay;
+    ofl::GridView view{};
+    bool pending = false;  // device work issued since the last synchronisation
+
+    bool gosa_on_dev = false;
+    double gosa_host = 0.0;
+
+    ofl_stats stats{};
+    bool profiling = false;
+    std::vector<hipEvent_t> ev;   // pairs (start, end)
+    std::vector<int> ev_nest;     // nest of each pair in use
+    size_t ev_used = 0;
+
+    bool broken = false;
+    int batch_refs = 0;
+};
+
+namespace ofl {
+
+ofl::TileCfg default_tile(int I);
+void grid_ensure_device(ofl_grid *g);
+void grid_sync(ofl_grid *g);
+void grid_exec(ofl_grid *g, const std::vector<Xfer> &xs);
+void *grid_array_ptr(ofl_grid *g, int a);
+void grid_run_loop(ofl_grid *g, int iters, float omega, int nests);
+double grid_fetch_gosa(ofl_grid *g);
+
+}  // namespace ofl

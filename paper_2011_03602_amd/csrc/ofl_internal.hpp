@@ -1,0 +1,107 @@
+// Internal declarations of the offloaded-Jacobi library: device layout, the
+// views the kernels read, launch entry points and the error type. Not part of
+// the public interface (that is include/ofl.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+#include "ofl.h"
+
+namespace ofl {
+
+constexpr int kNCoef = 12;
+constexpr int kWave = 64;
+constexpr int kPitchAlign = 32;   // elements: rows start on 128-byte boundaries (FP32)
+constexpr size_t kGuard = 1024;   // elements of slack before and after every device array
+constexpr int kResidualBlocks = 2048;  // fixed -> deterministic residual partials
+constexpr int kResidualThreads = 256;
+constexpr int kRowUnroll = 4;
+
+enum Nest { kS = 0, kR = 1, kC = 2 };
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] void fail(int code, const std::string &msg);
+void hip_check(hipError_t e, const char *what);
+
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// Device layout of one grid: every array pitched along i, rows 128-byte
+// aligned, with guard elements before and after so that whole-wave vector
+// loads that run past the last interior point stay inside the allocation.
+struct Layout {
+    int I = 0, J = 0, K = 0;
+    int pitch = 0;          // elements per row
+    size_t plane = 0;       // pitch * J
+    size_t elems = 0;       // pitch * J * K
+    size_t coef_elem = 4;   // bytes per stored coefficient (4 or 2)
+    size_t off[OFL_NARRAYS] = {};  // byte offset of element 0 of each array in the block
+    size_t staging_off = 0; // contiguous I*J*K*4-byte staging buffer for transfers
+    size_t partials_off = 0;
+    size_t gosa_off = 0;
+    size_t total = 0;       // bytes of the whole device block
+};
+
+Layout make_layout(int I, int J, int K, int coef_format);
+
+// What a kernel needs to address one grid on the device.
+struct GridView {
+    float *p;
+    float *wrk2;
+    const void *coef[kNCoef];  // float* (FP32) or uint16_t* (bfloat16 formats)
+    float bias[kNCoef];
+    int I, J, K, pitch;
+    long long plane;
+    double *partials;  // residual partial sums (batched: base of this grid's range)
+    double *gosa;      // device scalar
+};
+
+// Sweep work item (batched launch): grid, i-tile, j-block, k-chunk.
+struct SweepItem {
+    int grid, itile, jblock, kchunk;
+};
+// Residual / copy-back work item (batched launch): grid and a range of row tiles.
+struct RowItem {
+    int grid, first, count, partial;
+};
+
+struct TileCfg {
+    int vec = 4, rows = 4, kchunk = 32, flags = 0, occupancy = 0;
+};
+
+bool tile_valid(const ofl_tile &t, std::string *why);
+TileCfg to_cfg(const ofl_tile &t);
+ofl_tile to_tile(const TileCfg &c);
+
+__host__ __device__ inline int itiles(int I, int vec) { return (I - 2) / (kWave * vec) + 1; }
+
+// Single-grid launches (kernels.hip).
+void launch_sweep(const GridView &g, const TileCfg &t, int bf16, float omega, hipStream_t s);
+void launch_residual(const GridView &g, int vec, int sum_mode, float omega, hipStream_t s);
+void launch_copyback(const GridView &g, int vec, hipStream_t s);
+void launch_pack(const void *staging, void *arr, int I, int J, int K, int pitch, int elem_bytes, hipStream_t s);
+void launch_unpack(const void *arr, void *staging, int I, int J, int K, int pitch, int elem_bytes, hipStream_t s);
+void launch_fill_zero(void *ptr, size_t bytes, hipStream_t s);
+void launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+
+// Batched launches (kernels.hip).
+void launch_batch_sweep(const GridView *views, const SweepItem *items, int nitems, const TileCfg &t, int bf16,
+                        float omega, int grid_blocks, hipStream_t s);
+void launch_batch_residual(const GridView *views, const RowItem *items, int nitems, int vec, int sum_mode,
+                           int grid_blocks, hipStream_t s);
+void launch_batch_finalize(const GridView *views, const int *partial_range, int ngrids, float omega,
+                           hipStream_t s);
+void launch_batch_copyback(const GridView *views, const RowItem *items, int nitems, int vec, int grid_blocks,
+                           hipStream_t s);
+
+int device_cu_count(int device);
+
+}  // namespace ofl

@@ -1,0 +1,494 @@
+// Genetic-algorithm tile tuner, in the style of the paper's loop-offload
+// search (Sec. 4.2.2): the search space is encoded as bit genes, the initial
+// population is random, every individual is built and measured on the real
+// device, a gene that cannot be built scores zero (the paper drops loops whose
+// directive does not compile), a gene whose results differ from the original
+// CPU program beyond a tolerance is given infinite time (the paper's result
+// check), fitness comes from the measured time, and selection, crossover,
+// mutation and an unchanged copy of the best individuals form the next
+// generation for a set number of generations; the best gene wins.
+//
+// Gene layout (bit 0 first):
+//   bits 0-1  vec       00:1 01:2 10:4 11: not buildable
+//   bits 2-3  rows      1, 2, 4, 8
+//   bits 4-6  kchunk    4, 8, ..., 512
+//   bits 7-9  flags     OFL_TILE_NT_LOADS | OFL_TILE_NT_STORES | OFL_TILE_PREFETCH
+//   bits 10-11 (batch)  occupancy 0 (one work-group per item), 2, 4, 8 per CU
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <memory>
+#include <numeric>
+#include <vector>
+
+#include "abi_util.hpp"
+#include "batch.hpp"
+
+namespace ofl {
+
+namespace {
+
+constexpr double kInf = std::numeric_limits<double>::infinity();
+
+struct Rng {
+    uint64_t s;
+    uint64_t next() {
+        uint64_t z = (s += 0x9E3779B97F4A7C15ULL);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+        return z ^ (z >> 31);
+    }
+    double uniform() { return static_cast<double>(next() >> 11) * 0x1.0p-53; }
+};
+
+int gene_bits(bool batch) { return batch ? 12 : 10; }
+
+bool decode(uint32_t gene, bool batch, TileCfg *t) {
+    const int v = static_cast<int>(gene & 3u);
+    if (v == 3)
+        return false;
+    t->vec = v == 0 ? 1 : (v == 1 ? 2 : 4);
+    t->rows = 1 << ((gene >> 2) & 3u);
+    t->kchunk = 4 << ((gene >> 4) & 7u);
+    t->flags = static_cast<int>((gene >> 7) & 7u);
+    const int occ = static_cast<int>((gene >> 10) & 3u);
+    t->occupancy = batch ? (occ == 0 ? 0 : (1 << occ)) : 0;
+    return true;
+}
+
+uint32_t encode(const TileCfg &t, bool batch) {
+    uint32_t g = t.vec == 1 ? 0u : (t.vec == 2 ? 1u : 2u);
+    int r = 0;
+    while ((1 << r) < t.rows && r < 3)
+        ++r;
+    g |= static_cast<uint32_t>(r) << 2;
+    int k = 0;
+    while ((4 << k) < t.kchunk && k < 7)
+        ++k;
+    g |= static_cast<uint32_t>(k) << 4;
+    g |= static_cast<uint32_t>(t.flags & 7) << 7;
+    if (batch) {
+        int o = 0;
+        while (o < 3 && (1 << o) < t.occupancy)
+            ++o;
+        g |= static_cast<uint32_t>(t.occupancy == 0 ? 0 : o) << 10;
+    }
+    return g;
+}
+
+// Small ragged check problem in the workload's value ranges (private to the
+// tuner's result check).
+struct CheckProblem {
+    int I, J, K;
+    std::vector<float> coef[kNCoef];
+    std::vector<float> p0;
+};
+
+CheckProblem make_check(int I, int J, int K, uint64_t seed) {
+    CheckProblem c{I, J, K, {}, {}};
+    const size_t n = static_cast<size_t>(I) * J * K;
+    Rng r{seed};
+    auto sym = [&](double h) { return static_cast<float>(h * (2.0 * r.uniform() - 1.0)); };
+    for (int a = 0; a < kNCoef; ++a)
+        c.coef[a].resize(n);
+    c.p0.resize(n);
+    for (size_t t = 0; t < n; ++t) {
+        const float a0 = 1.0f + sym(0.05), a1 = 1.0f + sym(0.05), a2 = 1.0f + sym(0.05);
+        c.coef[0][t] = a0;
+        c.coef[1][t] = a1;
+        c.coef[2][t] = a2;
+        c.coef[3][t] = static_cast<float>(1.0 / (2.0 * (static_cast<double>(a0) + a1 + a2)));
+        for (int b = 4; b < 7; ++b)
+            c.coef[b][t] = sym(0.01);
+        for (int b = 7; b < 10; ++b)
+            c.coef[b][t] = 1.0f;
+        c.coef[11][t] = sym(0.1);
+        c.p0[t] = static_cast<float>(r.uniform());
+    }
+    for (int k = 0; k < K; ++k)
+        for (int j = 0; j < J; ++j)
+            for (int i = 0; i < I; ++i) {
+                const bool in = i > 0 && j > 0 && k > 0 && i < I - 1 && j < J - 1 && k < K - 1;
+                c.coef[10][static_cast<size_t>(i) + static_cast<size_t>(I) * (j + static_cast<size_t>(J) * k)] =
+                    in ? 1.0f : 0.0f;
+            }
+    return c;
+}
+
+struct HostRun {
+    std::vector<float> p, wrk2;
+    ofl_grid *g = nullptr;
+    ~HostRun() { ofl_grid_destroy(g); }
+};
+
+void open_check_grid(const CheckProblem &c, int fmt, int sum_mode, int device, HostRun &h) {
+    h.p = c.p0;
+    h.wrk2.assign(c.p0.size(), 0.f);
+    ofl_grid_desc d{};
+    d.I = c.I;
+    d.J = c.J;
+    d.K = c.K;
+    d.coef_format = fmt;
+    d.sum_mode = sum_mode;
+    d.p = h.p.data();
+    d.wrk2 = h.wrk2.data();
+    for (int a = 0; a < kNCoef; ++a)
+        d.coef[a] = c.coef[a].data();
+    d.device = device;
+    if (ofl_grid_create(&d, &h.g) != OFL_OK)
+        fail(OFL_EINVAL, std::string("tuner check grid: ") + ofl_last_error());
+}
+
+// Relative max-norm difference of two iterates over the interior.
+double rel_diff(const CheckProblem &c, const std::vector<float> &x, const std::vector<float> &ref) {
+    double num = 0.0, den = 0.0;
+    for (int k = 1; k < c.K - 1; ++k)
+        for (int j = 1; j < c.J - 1; ++j)
+            for (int i = 1; i < c.I - 1; ++i) {
+                const size_t t = static_cast<size_t>(i) + static_cast<size_t>(c.I) * (j + static_cast<size_t>(c.J) * k);
+                num = std::max(num, std::fabs(static_cast<double>(x[t]) - ref[t]));
+                den = std::max(den, std::fabs(static_cast<double>(ref[t])));
+            }
+    return den > 0 ? num / den : num;
+}
+
+constexpr int kCheckIters = 3;
+constexpr float kCheckOmega = 0.8f;
+
+// Does the tile reproduce the all-CPU nests on small ragged grids?
+bool tile_correct(const TileCfg &t, bool batch, int fmt, int sum_mode, int device, double tol) {
+    const int I = kWave * t.vec + 37;
+    const int J = 2 * t.rows + 3;
+    const int K = std::min(t.kchunk, 24) + 7;
+    std::vector<CheckProblem> probs;
+    probs.push_back(make_check(I, J, K, 0xC0FFEEULL + static_cast<uint64_t>(I * 131 + J * 7 + K)));
+    if (batch) {
+        probs.push_back(make_check(std::max(3, I / 3), J + 1, K + 2, 0xBEEFULL + 17));
+        probs.push_back(make_check(5, 4, 3, 0xBEEFULL + 29));
+    }
+    std::vector<std::unique_ptr<HostRun>> gpu(probs.size()), cpu(probs.size());
+    std::vector<double> g_gosa(probs.size()), c_gosa(probs.size());
+    for (size_t q = 0; q < probs.size(); ++q) {
+        gpu[q].reset(new HostRun);
+        cpu[q].reset(new HostRun);
+        open_check_grid(probs[q], fmt, sum_mode, device, *gpu[q]);
+        open_check_grid(probs[q], fmt, sum_mode, device, *cpu[q]);
+        if (ofl_set_offload_mask(cpu[q]->g, OFL_MASK_ALL_CPU, OFL_XFER_HOISTED) != OFL_OK ||
+            ofl_jacobi_run(cpu[q]->g, kCheckIters, kCheckOmega, &c_gosa[q]) != OFL_OK)
+            fail(OFL_EDEVICE, std::string("tuner reference run: ") + ofl_last_error());
+    }
+    if (batch) {
+        std::vector<ofl_grid *> gs;
+        for (auto &h : gpu)
+            gs.push_back(h->g);
+        ofl_batch *b = nullptr;
+        const ofl_tile tile = to_tile(t);
+        if (ofl_batch_create(gs.data(), static_cast<int>(gs.size()), &tile, &b) != OFL_OK)
+            fail(OFL_EDEVICE, std::string("tuner check batch: ") + ofl_last_error());
+        const int rc = ofl_batch_run(b, kCheckIters, kCheckOmega, g_gosa.data());
+        ofl_batch_destroy(b);
+        if (rc != OFL_OK)
+            fail(rc, std::string("tuner check batch run: ") + ofl_last_error());
+    } else {
+        const ofl_tile tile = to_tile(t);
+        if (ofl_set_tile(gpu[0]->g, &tile) != OFL_OK ||
+            ofl_jacobi_run(gpu[0]->g, kCheckIters, kCheckOmega, &g_gosa[0]) != OFL_OK)
+            fail(OFL_EDEVICE, std::string("tuner check run: ") + ofl_last_error());
+    }
+    for (size_t q = 0; q < probs.size(); ++q) {
+        if (!(rel_diff(probs[q], gpu[q]->p, cpu[q]->p) <= tol))
+            return false;
+        const double gd = std::fabs(g_gosa[q] - c_gosa[q]) / std::max(std::fabs(c_gosa[q]), 1e-300);
+        if (!(gd <= 10.0 * tol))
+            return false;
+    }
+    return true;
+}
+
+double median(std::vector<double> v) {
+    std::sort(v.begin(), v.end());
+    const size_t n = v.size();
+    return n % 2 ? v[n / 2] : 0.5 * (v[n / 2 - 1] + v[n / 2]);
+}
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    EventPair() {
+        hip_check(hipEventCreate(&a), "hipEventCreate");
+        hip_check(hipEventCreate(&b), "hipEventCreate");
+    }
+    ~EventPair() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+    double ms() const {
+        float t = 0.f;
+        hip_check(hipEventElapsedTime(&t, a, b), "hipEventElapsedTime");
+        return t;
+    }
+};
+
+// Time probe_iters iterations with the tile applied (median of repeats).
+double time_grid(ofl_grid *g, const TileCfg &t, const ofl_ga_params &ga) {
+    g->tile = t;
+    grid_run_loop(g, 1, kCheckOmega, 3);  // warm-up
+    grid_sync(g);
+    EventPair ev;
+    std::vector<double> ts;
+    for (int r = 0; r < ga.repeats; ++r) {
+        hip_check(hipEventRecord(ev.a, g->stream), "hipEventRecord");
+        grid_run_loop(g, ga.probe_iters, kCheckOmega, 3);
+        hip_check(hipEventRecord(ev.b, g->stream), "hipEventRecord");
+        grid_sync(g);
+        ts.push_back(ev.ms());
+    }
+    return median(ts);
+}
+
+double time_batch(ofl_batch *b, const TileCfg &t, const ofl_ga_params &ga) {
+    if (b->tile.vec != t.vec || b->tile.rows != t.rows || b->tile.kchunk != t.kchunk || b->tile.flags != t.flags ||
+        b->tile.occupancy != t.occupancy) {
+        const ofl_tile tile = to_tile(t);
+        if (ofl_batch_set_tile(b, &tile) != OFL_OK)
+            fail(OFL_EINVAL, ofl_last_error());
+    }
+    batch_build_tables(b);
+    batch_launch(b, ga.probe_iters, kCheckOmega);  // warm-up (captures the graph)
+    hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    EventPair ev;
+    std::vector<double> ts;
+    for (int r = 0; r < ga.repeats; ++r) {
+        hip_check(hipEventRecord(ev.a, b->stream), "hipEventRecord");
+        batch_launch(b, ga.probe_iters, kCheckOmega);
+        hip_check(hipEventRecord(ev.b, b->stream), "hipEventRecord");
+        hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+        ts.push_back(ev.ms());
+    }
+    return median(ts);
+}
+
+void check_params(const ofl_ga_params &ga) {
+    if (ga.population < 2 || ga.generations < 1 || ga.elite < 0 || ga.elite > ga.population || ga.probe_iters < 1 ||
+        ga.repeats < 1 || !(ga.crossover >= 0 && ga.crossover <= 1) || !(ga.mutation >= 0 && ga.mutation <= 1) ||
+        !(ga.tolerance > 0))
+        fail(OFL_EINVAL, "GA parameters out of range");
+}
+
+// The GA proper; evaluate(gene) returns time in ms, +inf for wrong results,
+// or NaN for genes that cannot be built.
+template <class Eval>
+void run_ga(const ofl_ga_params &ga, bool batch, uint32_t seed_gene, Eval &&evaluate, ofl_tune_result *out) {
+    const int bits = gene_bits(batch);
+    const uint32_t full = (1u << bits) - 1u;
+    Rng rng{ga.seed ^ 0x5EEDULL};
+    std::vector<uint32_t> pop(static_cast<size_t>(ga.population));
+    for (auto &g : pop)
+        g = static_cast<uint32_t>(rng.next()) & full;
+    pop[0] = seed_gene & full;  // the current tile competes too
+    std::map<uint32_t, double> memo;
+    int rejected = 0;
+    uint32_t best = pop[0];
+    double best_t = kInf;
+    auto eval = [&](uint32_t g) {
+        auto it = memo.find(g);
+        if (it != memo.end())
+            return it->second;
+        const double t = evaluate(g);
+        if (!(t < kInf))
+            ++rejected;
+        memo[g] = t;
+        return t;
+    };
+    auto fitness = [](double t) { return (t > 0 && t < kInf) ? 1.0 / std::sqrt(t) : 0.0; };
+    for (int gen = 0; gen < ga.generations; ++gen) {
+        std::vector<double> f(pop.size());
+        for (size_t i = 0; i < pop.size(); ++i) {
+            const double t = eval(pop[i]);
+            f[i] = fitness(t);
+            if (t < best_t) {
+                best_t = t;
+                best = pop[i];
+            }
+        }
+        if (gen + 1 == ga.generations)
+            break;
+        std::vector<size_t> order(pop.size());
+        for (size_t i = 0; i < order.size(); ++i)
+            order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return f[a] > f[b]; });
+        std::vector<uint32_t> next;
+        for (int e = 0; e < ga.elite; ++e)
+            next.push_back(pop[order[static_cast<size_t>(e)]]);
+        const double total = std::accumulate(f.begin(), f.end(), 0.0);
+        auto pick = [&]() -> uint32_t {
+            if (total <= 0)
+                return pop[static_cast<size_t>(rng.next() % pop.size())];
+            double x = rng.uniform() * total;
+            for (size_t i = 0; i < pop.size(); ++i) {
+                x -= f[i];
+                if (x < 0)
+                    return pop[i];
+            }
+            return pop.back();
+        };
+        while (static_cast<int>(next.size()) < ga.population) {
+            uint32_t a = pick(), b = pick();
+            if (rng.uniform() < ga.crossover) {
+                const int cut = 1 + static_cast<int>(rng.next() % static_cast<uint64_t>(bits - 1));
+                const uint32_t lo = (1u << cut) - 1u;
+                const uint32_t ca = (a & lo) | (b & ~lo);
+                const uint32_t cb = (b & lo) | (a & ~lo);
+                a = ca;
+                b = cb;
+            }
+            for (uint32_t *c : {&a, &b}) {
+                for (int bit = 0; bit < bits; ++bit)
+                    if (rng.uniform() < ga.mutation)
+                        *c ^= 1u << bit;
+                if (static_cast<int>(next.size()) < ga.population)
+                    next.push_back(*c & full);
+            }
+        }
+        pop.swap(next);
+    }
+    TileCfg t;
+    if (!(best_t < kInf) || !decode(best, batch, &t))
+        fail(OFL_ESTATE, "no gene produced a correct result");
+    out->best = to_tile(t);
+    out->best_ms = best_t;
+    out->evaluated = static_cast<int>(memo.size());
+    out->rejected = rejected;
+}
+
+ofl_ga_params defaults_or(const ofl_ga_params *ga) {
+    if (ga)
+        return *ga;
+    ofl_ga_params d;
+    d.population = 16;
+    d.generations = 12;
+    d.seed = 2011036020ULL;
+    d.crossover = 0.9;
+    d.mutation = 0.05;
+    d.elite = 1;
+    d.probe_iters = 5;
+    d.repeats = 3;
+    d.tolerance = 1e-5;
+    return d;
+}
+
+}  // namespace
+
+}  // namespace ofl
+
+using namespace ofl;
+
+extern "C" {
+
+int ofl_grid_tune(ofl_grid *g, const ofl_ga_params *ga_in, ofl_tune_result *out) {
+    return guarded(nullptr, [&] {
+        if (!g || !out)
+            fail(OFL_EINVAL, "NULL argument");
+        if (g->broken)
+            fail(OFL_EDEVICE, "grid handle unusable after an earlier device error");
+        const ofl_ga_params ga = defaults_or(ga_in);
+        check_params(ga);
+        // Bring p home and keep a copy: the timing runs iterate on the device.
+        grid_ensure_device(g);
+        {
+            std::vector<Xfer> xs;
+            plan_sync_host(-1, g->valid, xs);
+            grid_exec(g, xs);
+            grid_sync(g);
+        }
+        std::vector<float> saved(g->p, g->p + g->n);
+        const unsigned mask = g->mask;
+        const int mode = g->mode;
+        const TileCfg old = g->tile;
+        g->mask = OFL_MASK_ALL_GPU;
+        g->mode = OFL_XFER_HOISTED;
+        std::map<uint32_t, bool> checked;
+        auto evaluate = [&](uint32_t gene) -> double {
+            TileCfg t;
+            if (!decode(gene, false, &t))
+                return kInf;
+            const uint32_t key = gene & 0x3ffu;
+            auto it = checked.find(key);
+            const bool ok = it != checked.end()
+                                ? it->second
+                                : (checked[key] = tile_correct(t, false, g->fmt, g->sum_mode, g->device, ga.tolerance));
+            if (!ok)
+                return kInf;
+            return time_grid(g, t, ga);
+        };
+        ofl_tune_result res{};
+        try {
+            run_ga(ga, false, encode(old, false), evaluate, &res);
+        } catch (...) {
+            g->mask = mask;
+            g->mode = mode;
+            g->tile = old;
+            throw;
+        }
+        grid_sync(g);
+        std::memcpy(g->p, saved.data(), saved.size() * sizeof(float));
+        g->valid.host[OFL_ARR_P] = 1;
+        g->valid.dev[OFL_ARR_P] = 0;
+        g->mask = mask;
+        g->mode = mode;
+        g->tile = to_cfg(res.best);
+        *out = res;
+    });
+}
+
+int ofl_batch_tune(ofl_batch *b, const ofl_ga_params *ga_in, ofl_tune_result *out) {
+    return guarded(nullptr, [&] {
+        if (!b || !out)
+            fail(OFL_EINVAL, "NULL argument");
+        const ofl_ga_params ga = defaults_or(ga_in);
+        check_params(ga);
+        hip_check(hipSetDevice(b->device), "hipSetDevice");
+        std::vector<std::vector<float>> saved;
+        for (ofl_grid *g : b->grids) {
+            std::vector<Xfer> xs;
+            plan_sync_host(-1, g->valid, xs);
+            grid_exec(g, xs);
+            grid_sync(g);
+            saved.emplace_back(g->p, g->p + g->n);
+        }
+        batch_prepare(b);
+        const TileCfg old = b->tile;
+        std::map<uint32_t, bool> checked;
+        auto evaluate = [&](uint32_t gene) -> double {
+            TileCfg t;
+            if (!decode(gene, true, &t))
+                return kInf;
+            auto it = checked.find(gene);
+            const bool ok = it != checked.end()
+                                ? it->second
+                                : (checked[gene] = tile_correct(t, true, b->fmt, b->sum_mode, b->device, ga.tolerance));
+            if (!ok)
+                return kInf;
+            const double ms = time_batch(b, t, ga);
+            batch_mark_done(b, 0);
+            return ms;
+        };
+        ofl_tune_result res{};
+        run_ga(ga, true, encode(old, true), evaluate, &res);
+        const ofl_tile best = res.best;
+        if (ofl_batch_set_tile(b, &best) != OFL_OK)
+            fail(OFL_EINVAL, ofl_last_error());
+        for (size_t t = 0; t < b->grids.size(); ++t) {
+            ofl_grid *g = b->grids[t];
+            std::memcpy(g->p, saved[t].data(), saved[t].size() * sizeof(float));
+            g->valid.host[OFL_ARR_P] = 1;
+            g->valid.dev[OFL_ARR_P] = 0;
+            g->valid.dev[OFL_ARR_WRK2] = 1;
+            g->valid.host[OFL_ARR_WRK2] = 0;
+        }
+        *out = res;
+    });
+}
+
+}  // extern "C"

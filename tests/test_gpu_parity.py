@@ -1,0 +1,381 @@
+"""GPU parity: the HIP path (through the C interface) against the FP64 oracle
+on the same seeded inputs, element by element over the interior.
+
+Bars: FP32 p max-norm relative error <= 1e-5 and residual relative error <=
+1e-4; bfloat16-offset storage and batched forms <= 1e-3 against the oracle
+on the FP32 inputs. The boundary layer must come back bitwise unchanged.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2011_03602_amd as ofl
+import synth
+from helpers import (OMEGA, TOL_BF16, TOL_GOSA_F32, TOL_P_F32, boundary_equal, p_rel_err, rel_err)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # collected on CPU hosts, skipped there
+    pytestmark = [pytest.mark.gpu, pytest.mark.skip(reason="needs a GPU")]
+
+
+def say(*args):
+    print("[gpu]", *args, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(arrays, iters, mask=ofl.OFL_MASK_ALL_GPU, mode=ofl.OFL_XFER_HOISTED, tile=None, fmt=ofl.OFL_COEF_F32,
+            sum_mode=ofl.OFL_SUM_F64, torch_memory=False):
+    g = ofl.Grid(arrays, coef_format=fmt, sum_mode=sum_mode, torch_memory=torch_memory)
+    ofl.ofl_set_offload_mask(g.handle, mask, mode)
+    if tile is not None:
+        ofl.ofl_set_tile(g.handle, tile)
+    gosa = ofl.ofl_jacobi_run(g.handle, iters, OMEGA)
+    return g, gosa
+
+
+def check_against_oracle(arrays, g, gosa, iters, tol_p=TOL_P_F32, tol_g=TOL_GOSA_F32, ref=None):
+    p_ref, g_ref = ref if ref is not None else oracle.jacobi(arrays, iters, float(OMEGA))
+    pe, ge = p_rel_err(g.p, p_ref), rel_err(gosa, g_ref)
+    assert pe <= tol_p, f"p rel err {pe:.3e}"
+    assert ge <= tol_g, f"gosa rel err {ge:.3e}"
+    assert boundary_equal(g.p, arrays["p"])
+    return pe, ge
+
+
+# ------------------------------------------------------------ small config
+
+
+@pytest.mark.parametrize("mask", [ofl.OFL_MASK_ALL_CPU, ofl.OFL_MASK_ALL_GPU])
+def test_33x33x65_50_iterations(mask):
+    say("33x33x65 x50, mask", mask)
+    a = synth.make_problem(33, 33, 65)
+    g, gosa = run_gpu(a, 50, mask=mask)
+    check_against_oracle(a, g, gosa, 50)
+    s = ofl.ofl_get_stats(g.handle)
+    if mask == ofl.OFL_MASK_ALL_GPU:
+        assert list(s.gpu_nests) == [50] * 3 and list(s.cpu_nests) == [0] * 3
+        assert s.h2d_count == 13 and s.d2h_count == 1
+    g.close()
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    a = synth.make_problem(70, 37, 29, seed=77)
+    return a, oracle.jacobi(a, 12, float(OMEGA))
+
+
+@pytest.mark.parametrize("mode", [ofl.OFL_XFER_PER_ITER, ofl.OFL_XFER_HOISTED])
+@pytest.mark.parametrize("mask", range(8))
+def test_every_mask_and_placement(ragged, mask, mode):
+    say("70x37x29 x12 mask", mask, "mode", mode)
+    a, ref = ragged
+    g, gosa = run_gpu(a, 12, mask=mask, mode=mode)
+    check_against_oracle(a, g, gosa, 12, ref=ref)
+    s = ofl.ofl_get_stats(g.handle)
+    xs, _, _ = ofl.ofl_plan(mask, mode, 12, True)
+    assert s.h2d_count == len([x for x in xs if x[4] == 0])
+    assert s.d2h_count == len([x for x in xs if x[4] == 1])
+    for nest in range(3):
+        on_gpu = (mask >> nest) & 1
+        assert s.gpu_nests[nest] == (12 if on_gpu else 0)
+        assert s.cpu_nests[nest] == (0 if on_gpu else 12)
+    g.close()
+
+
+TILES = [
+    ofl.tile(vec=1, rows=1, kchunk=1),
+    ofl.tile(vec=1, rows=3, kchunk=5, flags=ofl.OFL_TILE_NT_LOADS),
+    ofl.tile(vec=2, rows=8, kchunk=64, flags=ofl.OFL_TILE_PREFETCH),
+    ofl.tile(vec=2, rows=2, kchunk=7, flags=ofl.OFL_TILE_NT_STORES),
+    ofl.tile(vec=4, rows=4, kchunk=32, flags=0),
+    ofl.tile(vec=4, rows=5, kchunk=3, flags=7),
+    ofl.tile(vec=4, rows=8, kchunk=1024, flags=ofl.OFL_TILE_PREFETCH | ofl.OFL_TILE_NT_LOADS),
+]
+
+
+@pytest.fixture(scope="module")
+def wide():
+    # 300 points along i: two or more i-tiles at every vector width, ragged ends
+    a = synth.make_problem(300, 19, 23, seed=5)
+    return a, oracle.jacobi(a, 4, float(OMEGA))
+
+
+@pytest.mark.parametrize("t", TILES, ids=lambda t: f"v{t.vec}r{t.rows}k{t.kchunk}f{t.flags}")
+def test_tiles(wide, t):
+    say("300x19x23 x4 tile", t.as_dict())
+    a, ref = wide
+    g, gosa = run_gpu(a, 4, tile=t)
+    check_against_oracle(a, g, gosa, 4, ref=ref)
+    g.close()
+
+
+@pytest.mark.parametrize("dims", [(3, 3, 3), (3, 5, 4), (4, 3, 3), (5, 3, 7), (258, 3, 3), (66, 4, 5), (65, 6, 3),
+                                  (130, 3, 4), (257, 5, 4)])
+@pytest.mark.parametrize("vec", [1, 2, 4])
+def test_edge_shapes(dims, vec):
+    say("edge", dims, "vec", vec)
+    a = synth.make_problem(*dims, seed=sum(dims))
+    g, gosa = run_gpu(a, 3, tile=ofl.tile(vec=vec, rows=2, kchunk=2))
+    check_against_oracle(a, g, gosa, 3)
+    g.close()
+
+
+def test_zero_iterations_on_gpu():
+    say("zero iterations")
+    a = synth.make_problem(9, 8, 7)
+    g, gosa = run_gpu(a, 0)
+    assert np.isnan(gosa) and np.array_equal(g.p, a["p"])
+    g.close()
+
+
+# --------------------------------------------------------- full-size configs
+
+
+def test_129x129x257_200_iterations():
+    say("129x129x257 x200 mask 7 hoisted")
+    a = synth.make_problem(129, 129, 257)
+    g, gosa = run_gpu(a, 200)
+    pe, ge = check_against_oracle(a, g, gosa, 200)
+    say(f"  p rel {pe:.2e} gosa rel {ge:.2e}")
+    g.close()
+
+
+@pytest.fixture(scope="module")
+def headline():
+    say("generating 257x257x513")
+    return synth.make_problem(257, 257, 513)
+
+
+def test_257x257x513_first_iterations(headline):
+    say("257x257x513 x2 full compare")
+    a = headline
+    g, gosa = run_gpu(a, 2)
+    pe, ge = check_against_oracle(a, g, gosa, 2)
+    say(f"  p rel {pe:.2e} gosa rel {ge:.2e}")
+    g.close()
+
+
+def test_257x257x513_100th_iteration(headline):
+    """The 100-iteration run in the benchmark's configuration: after 99
+    iterations inside a data region, fetch p; the 100th step must equal one
+    oracle sweep applied to exactly that FP32 iterate."""
+    say("257x257x513 x100 in a data region")
+    a = headline
+    g = ofl.Grid(a, torch_memory=True)
+    ofl.ofl_set_offload_mask(g.handle, 7, ofl.OFL_XFER_HOISTED)
+    ofl.ofl_data_enter(g.handle)
+    ofl.ofl_jacobi_run(g.handle, 99, OMEGA)
+    assert np.array_equal(g.p, a["p"])  # nothing came home inside the region
+    ofl.ofl_update_host(g.handle)
+    p99 = g.p.copy()
+    gosa100 = ofl.ofl_jacobi_run(g.handle, 1, OMEGA)
+    ofl.ofl_data_exit(g.handle)
+    assert boundary_equal(g.p, a["p"])
+    w_ref, g_ref = oracle.sweep(dict(a, p=p99), float(OMEGA))
+    p_ref = p99.astype(np.float64)
+    p_ref[1:-1, 1:-1, 1:-1] = w_ref[1:-1, 1:-1, 1:-1]
+    pe, ge = p_rel_err(g.p, p_ref), rel_err(gosa100, g_ref)
+    say(f"  step-100 p rel {pe:.2e} gosa rel {ge:.2e}")
+    assert pe <= TOL_P_F32 and ge <= TOL_GOSA_F32
+    g.close()
+
+
+# ------------------------------------------------------ formats and residual
+
+
+@pytest.fixture(scope="module")
+def mid():
+    a = synth.make_problem(129, 129, 65, seed=11)
+    return a, oracle.jacobi(a, 50, float(OMEGA))
+
+
+def test_bf16_offset_storage(mid):
+    say("bf16-offset 129x129x65 x50")
+    a, ref = mid
+    g, gosa = run_gpu(a, 50, fmt=ofl.OFL_COEF_BF16_OFFSET)
+    pe, ge = check_against_oracle(a, g, gosa, 50, tol_p=TOL_BF16, tol_g=TOL_BF16, ref=ref)
+    say(f"  vs FP32-input oracle: p rel {pe:.2e} gosa rel {ge:.2e}")
+    bias = ofl.ofl_grid_coef_bias(g.handle)
+    dec = dict(a)
+    for n, name in enumerate(ofl.COEF_NAMES):
+        dec[name] = oracle.offset_bf16_decode(a[name], bias[n])
+    pe2, ge2 = check_against_oracle(dec, g, gosa, 50)
+    say(f"  vs decoded-input oracle: p rel {pe2:.2e} gosa rel {ge2:.2e}")
+    g.close()
+
+
+def test_bf16_plain_storage_matches_decoded_inputs(mid):
+    say("bf16-plain 129x129x65 x50")
+    a, _ = mid
+    g, gosa = run_gpu(a, 50, fmt=ofl.OFL_COEF_BF16)
+    dec = {k: (oracle.bf16_rne(v) if k in ofl.COEF_NAMES else v) for k, v in a.items()}
+    check_against_oracle(dec, g, gosa, 50)
+    g.close()
+
+
+@pytest.mark.parametrize("fmt", [ofl.OFL_COEF_F32, ofl.OFL_COEF_BF16_OFFSET])
+def test_compensated_fp32_residual(mid, fmt):
+    say("kahan residual fmt", fmt)
+    a, ref = mid
+    g, gosa = run_gpu(a, 50, fmt=fmt, sum_mode=ofl.OFL_SUM_KAHAN_F32)
+    tol = TOL_GOSA_F32 if fmt == ofl.OFL_COEF_F32 else TOL_BF16
+    assert rel_err(gosa, ref[1]) <= tol
+    g.close()
+
+
+def test_residual_entry_point_on_gpu():
+    say("ofl_residual")
+    a = synth.make_problem(67, 45, 37, seed=3)
+    g = ofl.Grid(a)
+    r = ofl.ofl_residual(g.handle)
+    assert rel_err(r, oracle.residual(a)) <= TOL_GOSA_F32
+    assert np.array_equal(g.p, a["p"])
+    g.close()
+
+
+def test_torch_memory_and_stream():
+    say("torch arena + stream")
+    a = synth.make_problem(40, 33, 21, seed=8)
+    g, gosa = run_gpu(a, 10, torch_memory=True)
+    check_against_oracle(a, g, gosa, 10)
+    g.close()
+
+
+# ------------------------------------------------ determinism and semantics
+
+
+def test_bitwise_deterministic():
+    say("determinism")
+    a = synth.make_problem(129, 67, 45, seed=12)
+    g1, r1 = run_gpu(a, 20)
+    g2, r2 = run_gpu(a, 20)
+    assert np.array_equal(g1.p, g2.p) and r1 == r2
+    g1.close()
+    g2.close()
+
+
+def test_split_runs_in_data_region_equal_one_run():
+    say("split runs")
+    a = synth.make_problem(80, 40, 30, seed=13)
+    g1, r1 = run_gpu(a, 10)
+    g2 = ofl.Grid(a)
+    ofl.ofl_data_enter(g2.handle)
+    ofl.ofl_jacobi_run(g2.handle, 4, OMEGA)
+    r2 = ofl.ofl_jacobi_run(g2.handle, 6, OMEGA)
+    ofl.ofl_data_exit(g2.handle)
+    assert np.array_equal(g1.p, g2.p) and r1 == r2
+    s = ofl.ofl_get_stats(g2.handle)
+    assert s.h2d_count == 13 and s.d2h_count == 1
+    g1.close()
+    g2.close()
+
+
+def test_profiling_counts_every_gpu_nest():
+    say("profiling")
+    a = synth.make_problem(65, 33, 33, seed=14)
+    g = ofl.Grid(a)
+    ofl.ofl_set_profiling(g.handle, True)
+    ofl.ofl_jacobi_run(g.handle, 7, OMEGA)
+    s = ofl.ofl_get_stats(g.handle)
+    assert list(s.timed_nests) == [7, 7, 7]
+    assert all(ms > 0 for ms in s.kernel_ms)
+    g.close()
+
+
+def test_device_copy_kernel():
+    say("device copy")
+    src = torch.arange(1 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.zeros_like(src)
+    ofl.ofl_device_copy(dst.data_ptr(), src.data_ptr(), src.numel() * 4, None)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
+
+
+# ------------------------------------------------------------------- batch
+
+
+def _small_batch(n=6):
+    sizes = [(37, 41, 67), (70, 33, 70), (130, 35, 66), (33, 33, 65), (161, 40, 80), (50, 90, 70)][:n]
+    return [synth.make_problem(I, J, K, seed=synth.grid_seed(t)) for t, (I, J, K) in enumerate(sizes)]
+
+
+@pytest.mark.parametrize("fmt", [ofl.OFL_COEF_F32, ofl.OFL_COEF_BF16_OFFSET])
+@pytest.mark.parametrize("occupancy", [0, 2])
+def test_batch_matches_oracle_and_single_runs(fmt, occupancy):
+    say("batch fmt", fmt, "occupancy", occupancy)
+    probs = _small_batch()
+    tile = ofl.tile(vec=2, rows=4, kchunk=16, occupancy=occupancy)
+    grids = [ofl.Grid(a, coef_format=fmt) for a in probs]
+    b = ofl.ofl_batch_create([g.handle for g in grids], tile)
+    gosa = ofl.ofl_batch_run(b, 8, OMEGA, len(grids))
+    tol = TOL_P_F32 if fmt == ofl.OFL_COEF_F32 else TOL_BF16
+    tol_g = TOL_GOSA_F32 if fmt == ofl.OFL_COEF_F32 else TOL_BF16
+    for a, g, r in zip(probs, grids, gosa):
+        check_against_oracle(a, g, r, 8, tol_p=tol, tol_g=tol_g)
+    # the same tile on one grid at a time: identical per-point arithmetic -> identical p
+    for a, g in zip(probs, grids):
+        single, _ = run_gpu(a, 8, tile=ofl.tile(vec=2, rows=4, kchunk=16), fmt=fmt)
+        assert np.array_equal(single.p, g.p)
+        single.close()
+    ofl.ofl_batch_destroy(b)
+    for g in grids:
+        g.close()
+
+
+def test_batch_graph_replays_continue_the_iteration():
+    say("batch graph replay")
+    probs = _small_batch(4)
+    grids = [ofl.Grid(a) for a in probs]
+    b = ofl.ofl_batch_create([g.handle for g in grids], ofl.tile(vec=1, rows=2, kchunk=32))
+    for g in grids:
+        ofl.ofl_data_enter(g.handle)
+    ofl.ofl_batch_run(b, 3, OMEGA, len(grids))   # captures the graph
+    torch.cuda.synchronize()
+    ofl.ofl_batch_run(b, 3, OMEGA, len(grids))   # replays it
+    gosa = ofl.ofl_batch_run(b, 3, OMEGA, len(grids))  # and again
+    for g in grids:
+        ofl.ofl_data_exit(g.handle)
+    for a, g, r in zip(probs, grids, gosa):
+        check_against_oracle(a, g, r, 9)
+    ofl.ofl_batch_destroy(b)
+    for g in grids:
+        g.close()
+
+
+# -------------------------------------------------------------------- tuner
+
+
+def test_grid_tuner_small_search():
+    say("grid GA tuner")
+    a = synth.make_problem(67, 45, 37, seed=21)
+    g = ofl.Grid(a)
+    res = ofl.ofl_grid_tune(g.handle, ofl.ga_params(population=4, generations=2, probe_iters=2, repeats=1))
+    assert res.best_ms > 0 and res.evaluated >= 1
+    assert np.array_equal(g.p, a["p"])  # tuning leaves the iterate alone
+    t = ofl.ofl_get_tile(g.handle)
+    assert t.as_dict() == res.best.as_dict()
+    gosa = ofl.ofl_jacobi_run(g.handle, 5, OMEGA)
+    check_against_oracle(a, g, gosa, 5)
+    g.close()
+
+
+def test_batch_tuner_small_search():
+    say("batch GA tuner")
+    probs = _small_batch(3)
+    grids = [ofl.Grid(a) for a in probs]
+    b = ofl.ofl_batch_create([g.handle for g in grids])
+    res = ofl.ofl_batch_tune(b, ofl.ga_params(population=4, generations=2, probe_iters=2, repeats=1))
+    assert res.best_ms > 0
+    for a, g in zip(probs, grids):
+        assert np.array_equal(g.p, a["p"])
+    gosa = ofl.ofl_batch_run(b, 4, OMEGA, len(grids))
+    for a, g, r in zip(probs, grids, gosa):
+        check_against_oracle(a, g, r, 4)
+    ofl.ofl_batch_destroy(b)
+    for g in grids:
+        g.close()
