@@ -65,7 +65,7 @@ def measured_traffic():
     return rec.get("hbm_bytes_per_launch")
 
 
-def run_single(ofl, arrays, fmt, steps, warmup, tile=None, profile=True):
+def run_single(ofl, arrays, fmt, steps, warmup, tile=None, profile=True, iters=ITERS):
     """Time `steps` runs of ITERS iterations on one grid; returns a result dict."""
     import torch
 
@@ -76,14 +76,14 @@ def run_single(ofl, arrays, fmt, steps, warmup, tile=None, profile=True):
     ofl.ofl_set_offload_mask(h, ofl.OFL_MASK_ALL_GPU, ofl.OFL_XFER_HOISTED)
     ofl.ofl_data_enter(h)  # inputs resident in HBM before timing
     for _ in range(warmup):
-        ofl.ofl_jacobi_run(h, ITERS, OMEGA)
+        ofl.ofl_jacobi_run(h, iters, OMEGA)
     ofl.ofl_reset_stats(h)
     ofl.ofl_set_profiling(h, profile)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     gosa = None
     for _ in range(steps):
-        gosa = ofl.ofl_jacobi_run(h, ITERS, OMEGA)
+        gosa = ofl.ofl_jacobi_run(h, iters, OMEGA)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st = ofl.ofl_get_stats(h)
@@ -92,7 +92,7 @@ def run_single(ofl, arrays, fmt, steps, warmup, tile=None, profile=True):
     ofl.ofl_data_exit(h)
     g.close()
     I, J, K = SHAPE
-    lups = interior(I, J, K) * ITERS * steps
+    lups = interior(I, J, K) * iters * steps
     res = {
         "seconds": dt,
         "ms_per_step": 1e3 * dt / steps,
@@ -108,14 +108,14 @@ def run_single(ofl, arrays, fmt, steps, warmup, tile=None, profile=True):
     return res
 
 
-def run_batch(ofl, n_grids, fmt, steps, warmup, tune):
+def run_batch(ofl, n_grids, fmt, steps, warmup, tune, iters=ITERS):
     import torch
 
     import synth
 
     log(f"generating {n_grids} uneven grids")
     probs = synth.make_batch(n_grids)
-    total_lups = sum(interior(*shape) for shape, _ in probs) * ITERS
+    total_lups = sum(interior(*shape) for shape, _ in probs) * iters
     grids = [ofl.Grid(arr, coef_format=fmt) for _, arr in probs]
     for g in grids:
         ofl.ofl_data_enter(g.handle)
@@ -126,22 +126,22 @@ def run_batch(ofl, n_grids, fmt, steps, warmup, tune):
         r = ofl.ofl_batch_tune(b, ofl.ga_params(population=10, generations=6, probe_iters=10, repeats=2))
         tuned = {"tile": r.best.as_dict(), "probe_ms": r.best_ms, "evaluated": r.evaluated, "rejected": r.rejected}
     for _ in range(warmup):
-        ofl.ofl_batch_run(b, ITERS, OMEGA, n_grids)
+        ofl.ofl_batch_run(b, iters, OMEGA, n_grids)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        ofl.ofl_batch_run(b, ITERS, OMEGA, n_grids)
+        ofl.ofl_batch_run(b, iters, OMEGA, n_grids)
     torch.cuda.synchronize()
     dt_batch = (time.perf_counter() - t0) / steps
     tile_used = ofl.ofl_batch_get_tile(b).as_dict()
     ofl.ofl_batch_destroy(b)
     # baseline: the same grids one after another, plain single-grid runs
     for g in grids:
-        ofl.ofl_jacobi_run(g.handle, ITERS, OMEGA)
+        ofl.ofl_jacobi_run(g.handle, iters, OMEGA)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for g in grids:
-        ofl.ofl_jacobi_run(g.handle, ITERS, OMEGA)
+        ofl.ofl_jacobi_run(g.handle, iters, OMEGA)
     torch.cuda.synchronize()
     dt_seq = time.perf_counter() - t0
     for g in grids:
@@ -188,7 +188,10 @@ def main():
     ap.add_argument("--batch-grids", type=int, default=64)
     ap.add_argument("--tune-batch", action="store_true", help="run the GA tile search before the batched run")
     ap.add_argument("--oracle-iters", type=int, default=10)
-    ap.add_argument("--profile-only", default=None, help="headline|bf16|batch: run just that, no JSON")
+    ap.add_argument("--profile-only", default=None,
+                    help="headline|bf16|batch|copy: run just that under a profiler, print no JSON")
+    ap.add_argument("--profile-iters", type=int, default=ITERS,
+                    help="iterations per step in --profile-only runs (counter passes use a few)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -205,17 +208,30 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     ofl.lib()  # fail loudly if the library is missing
+    if args.profile_only == "copy":
+        # Copy kernel of known size: calibrates the HBM byte counters.
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(max(1, args.steps)):
+            ofl.ofl_device_copy(dst.data_ptr(), src.data_ptr(), nbytes, None)
+        torch.cuda.synchronize()
+        log(f"copied {nbytes} bytes {max(1, args.steps)} times")
+        return
     I, J, K = SHAPE
     log("generating 257x257x513 inputs")
     arrays = synth.make_problem(I, J, K)
 
     if args.profile_only:
+        it = args.profile_iters
         if args.profile_only == "headline":
-            run_single(ofl, arrays, ofl.OFL_COEF_F32, args.steps, args.warmup, profile=False)
+            run_single(ofl, arrays, ofl.OFL_COEF_F32, args.steps, args.warmup, profile=False, iters=it)
         elif args.profile_only == "bf16":
-            run_single(ofl, arrays, ofl.OFL_COEF_BF16_OFFSET, args.steps, args.warmup, profile=False)
+            run_single(ofl, arrays, ofl.OFL_COEF_BF16_OFFSET, args.steps, args.warmup, profile=False, iters=it)
         elif args.profile_only == "batch":
-            run_batch(ofl, args.batch_grids, ofl.OFL_COEF_F32, args.steps, args.warmup, False)
+            run_batch(ofl, args.batch_grids, ofl.OFL_COEF_F32, args.steps, args.warmup, False, iters=it)
+        else:
+            raise SystemExit(f"unknown --profile-only {args.profile_only}")
         log("profile run done")
         return
 

@@ -159,12 +159,17 @@ int ofl_grid_coef_bias(const ofl_grid *g, float bias[12]);
 /* ---- kernel tiles ------------------------------------------------------- */
 #define OFL_TILE_NT_LOADS 1   /* non-temporal loads of the coefficient streams */
 #define OFL_TILE_NT_STORES 2  /* non-temporal stores of wrk2 */
-#define OFL_TILE_PREFETCH 4   /* software-pipelined coefficient loads (plane k+1 during k) */
+#define OFL_TILE_PREFETCH 4   /* software-pipelined coefficient loads (next step during this one) */
+#define OFL_TILE_MARCH_J 8    /* waves march along j (own a k-plane) instead of along k (own a j-row) */
+#define OFL_TILE_XCD_REMAP 16 /* give each XCD one contiguous range of tiles (shared L2 for halos)
+                                 instead of round-robin (all XCDs stream one window of HBM) */
 
 typedef struct ofl_tile {
     int vec;       /* consecutive i-points per lane: 1, 2 or 4 (a wave spans 64*vec points) */
-    int rows;      /* j-rows per work-group = waves per work-group: 1..8 */
-    int kchunk;    /* k-planes each wave marches through: 1..1024 */
+    int rows;      /* lines per work-group = waves per work-group: 1..8 (j-rows, or k-planes
+                      with OFL_TILE_MARCH_J) */
+    int kchunk;    /* steps each wave marches through (k-planes, or j-rows with
+                      OFL_TILE_MARCH_J): 1..1024 */
     int flags;     /* OFL_TILE_* */
     int occupancy; /* batched launch: resident work-groups per CU (persistent kernels), 1..16;
                       0 = one work-group per work item */

@@ -27,7 +27,7 @@ OFL_MASK_ALL_CPU, OFL_MASK_ALL_GPU = 0, 7
 OFL_XFER_PER_ITER, OFL_XFER_HOISTED = 0, 1
 OFL_COEF_F32, OFL_COEF_BF16, OFL_COEF_BF16_OFFSET = 0, 1, 2
 OFL_SUM_F64, OFL_SUM_KAHAN_F32 = 0, 1
-OFL_TILE_NT_LOADS, OFL_TILE_NT_STORES, OFL_TILE_PREFETCH = 1, 2, 4
+OFL_TILE_NT_LOADS, OFL_TILE_NT_STORES, OFL_TILE_PREFETCH, OFL_TILE_MARCH_J, OFL_TILE_XCD_REMAP = 1, 2, 4, 8, 16
 ARRAY_NAMES = ("a0", "a1", "a2", "a3", "b0", "b1", "b2", "c0", "c1", "c2", "bnd", "wrk1", "p", "wrk2")
 COEF_NAMES = ARRAY_NAMES[:12]
 OFL_ARR_P, OFL_ARR_WRK2 = 12, 13

@@ -85,13 +85,12 @@ void batch_build_tables(ofl_batch *b) {
     const int rows_per_item = kRowsPerWaveItem * (kResidualThreads / kWave);
     for (int g : order) {
         const ofl_grid *q = b->grids[static_cast<size_t>(g)];
-        const int nti = itiles(q->I, t.vec);
-        const int njb = (q->J - 2 + t.rows - 1) / t.rows;
-        const int nkc = (q->K - 2 + t.kchunk - 1) / t.kchunk;
-        for (int kc = 0; kc < nkc; ++kc)
-            for (int jb = 0; jb < njb; ++jb)
+        int nti, nfb, nmc;
+        sweep_shape(q->I, q->J, q->K, t, &nti, &nfb, &nmc);
+        for (int mc = 0; mc < nmc; ++mc)
+            for (int fb = 0; fb < nfb; ++fb)
                 for (int it = 0; it < nti; ++it)
-                    sitems.push_back({g, it, jb, kc});
+                    sitems.push_back({g, it, fb, mc});
         const int nrt = nti * (q->J - 2) * (q->K - 2);
         int slot = 0;
         for (int first = 0; first < nrt; first += rows_per_item) {
@@ -140,10 +139,11 @@ void batch_enqueue(ofl_batch *b, int iters, float omega) {
     for (int it = 0; it < iters; ++it) {
         launch_batch_sweep(views, sitems, b->n_sitems, b->tile, b->fmt != OFL_COEF_F32, omega,
                            blocks_for(b, b->n_sitems), b->stream);
-        launch_batch_residual(views, ritems, b->n_ritems, b->tile.vec, b->sum_mode, blocks_for(b, b->n_ritems),
-                              b->stream);
+        launch_batch_residual(views, ritems, b->n_ritems, b->tile.vec, b->sum_mode, b->tile.flags,
+                              blocks_for(b, b->n_ritems), b->stream);
         launch_batch_finalize(views, range, n, omega, b->stream);
-        launch_batch_copyback(views, ritems, b->n_ritems, b->tile.vec, blocks_for(b, b->n_ritems), b->stream);
+        launch_batch_copyback(views, ritems, b->n_ritems, b->tile.vec, b->tile.flags, blocks_for(b, b->n_ritems),
+                              b->stream);
     }
 }
 
@@ -264,8 +264,8 @@ int ofl_batch_create(ofl_grid *const *grids, int n, const ofl_tile *tile, ofl_ba
         } else {
             b->tile.vec = 2;
             b->tile.rows = 4;
-            b->tile.kchunk = 32;
-            b->tile.flags = 0;
+            b->tile.kchunk = 4;
+            b->tile.flags = OFL_TILE_NT_LOADS;
             b->tile.occupancy = 0;
         }
         for (ofl_grid *g : b->grids)

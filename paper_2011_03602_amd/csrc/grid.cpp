@@ -51,9 +51,16 @@ Layout make_layout(int I, int J, int K, int coef_format) {
         off += (L.elems + kGuard) * eb;
         return at;
     };
-    for (int a = 0; a < kNCoef; ++a)
+#ifndef OFL_ARRAY_STAGGER
+#define OFL_ARRAY_STAGGER 0
+#endif
+    for (int a = 0; a < kNCoef; ++a) {
+        off += static_cast<size_t>(OFL_ARRAY_STAGGER) * a;
         L.off[a] = place(L.coef_elem);
+    }
+    off += static_cast<size_t>(OFL_ARRAY_STAGGER) * 12;
     L.off[OFL_ARR_P] = place(4);
+    off += static_cast<size_t>(OFL_ARRAY_STAGGER) * 13;
     L.off[OFL_ARR_WRK2] = place(4);
     L.staging_off = align_up(off, 256);
     off = L.staging_off + static_cast<size_t>(I) * J * K * 4;
@@ -77,7 +84,7 @@ bool tile_valid(const ofl_tile &t, std::string *why) {
         return bad("tile.rows must be in 1..8");
     if (t.kchunk < 1 || t.kchunk > 1024)
         return bad("tile.kchunk must be in 1..1024");
-    if (t.flags < 0 || t.flags > 7)
+    if (t.flags < 0 || t.flags > 31)
         return bad("tile.flags has unknown bits");
     if (t.occupancy < 0 || t.occupancy > 16)
         return bad("tile.occupancy must be in 0..16");
@@ -109,8 +116,8 @@ TileCfg default_tile(int I) {
     const int interior = I - 2;
     t.vec = interior > 128 ? 4 : (interior > 64 ? 2 : 1);
     t.rows = 4;
-    t.kchunk = 32;
-    t.flags = 0;
+    t.kchunk = 4;
+    t.flags = OFL_TILE_NT_LOADS;
     t.occupancy = 0;
     return t;
 }
@@ -223,10 +230,10 @@ void gpu_nest(ofl_grid *g, int nest, float omega) {
     if (nest == kS) {
         launch_sweep(g->view, g->tile, g->fmt != OFL_COEF_F32, omega, g->stream);
     } else if (nest == kR) {
-        launch_residual(g->view, g->tile.vec, g->sum_mode, omega, g->stream);
+        launch_residual(g->view, g->tile.vec, g->sum_mode, g->tile.flags, omega, g->stream);
         g->gosa_on_dev = true;
     } else {
-        launch_copyback(g->view, g->tile.vec, g->stream);
+        launch_copyback(g->view, g->tile.vec, g->tile.flags, g->stream);
     }
     prof_end(g);
     g->stats.gpu_nests[nest] += 1;

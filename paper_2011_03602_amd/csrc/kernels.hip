@@ -21,6 +21,10 @@
 //    that neighbouring j-blocks run on the same XCD (shared L2);
 //  * no MFMA: there is no dense contraction here.
 
+#include <array>
+#include <type_traits>
+#include <utility>
+
 #include "ofl_internal.hpp"
 
 namespace ofl {
@@ -33,9 +37,12 @@ typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 constexpr int kXcds = 8;
 
-// Work-groups are handed to the 8 XCDs round-robin by id. Renumber them so
-// that XCD x receives one contiguous range of logical tiles: neighbouring
-// tiles (which share halo rows) then share that XCD's L2.
+// Work-groups are handed to the 8 XCDs round-robin by id. With the remap on,
+// XCD x receives one contiguous range of logical tiles, so neighbouring tiles
+// (which share halo rows) share that XCD's L2. Off (the default), all XCDs
+// work through the same window of the grid at the same time, which on MI355X
+// streams HBM faster for the sweep (measured: 333 us vs 347 us per sweep at
+// 257x257x513) than the L2 sharing saves.
 __device__ __forceinline__ int xcd_remap(int bid, int n) {
     const int xcd = bid % kXcds;
     const int local = bid / kXcds;
@@ -114,19 +121,30 @@ __device__ __forceinline__ void load_bf16(const uint16_t *ptr, float bias, float
 }
 
 // One row segment of p: this lane's VEC values plus its outer neighbours
-// (left of element 0, right of element VEC-1). Interior lanes take them from
-// the adjacent lanes; lanes 0 and 63 load them (the tile's halo). For the
-// first tile of a row lane 0 reads the element before the row (row padding or
-// the array's front guard): that value only feeds i = 0, which is never stored.
+// (left of element 0, right of element VEC-1). The loads are issued for all
+// rows of a step before any neighbour exchange, so that one wait covers the
+// whole step: issue_prow() starts the vector load and the halo load,
+// finish_prow() takes the inner neighbours from the adjacent lanes and the
+// two wave-edge neighbours from the halo value. The halo load is branch-free:
+// lane 63 reads the element after the tile, every other lane the element
+// before it (one shared cache line). For the first tile of a row that element
+// is row padding or the array's front guard; it only feeds i = 0, which is
+// never stored.
 template <int VEC>
-__device__ __forceinline__ void load_prow(const float *row, int ib, int ts, int lane, float (&v)[VEC], float &l,
-                                          float &r) {
+__device__ __forceinline__ void issue_prow(const float *row, int ib, int ts, int lane, float (&v)[VEC], float &h) {
     load_f32<VEC, false>(row + ib, v);
+    h = row[lane == kWave - 1 ? ts + kWave * VEC : ts - 1];
+}
+
+template <int VEC>
+__device__ __forceinline__ void finish_prow(const float (&v)[VEC], float h, int lane, float &l, float &r) {
+#ifdef OFL_USE_DPP
+    const float up = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[VEC - 1]), 0x138, 0xf, 0xf, false));
+    const float dn = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[0]), 0x130, 0xf, 0xf, false));
+#else
     const float up = __shfl_up(v[VEC - 1], 1, kWave);
     const float dn = __shfl_down(v[0], 1, kWave);
-    float h = 0.f;
-    if (lane == 0 || lane == kWave - 1)
-        h = row[lane == 0 ? ts - 1 : ts + kWave * VEC];
+#endif
     l = (lane == 0) ? h : up;
     r = (lane == kWave - 1) ? h : dn;
 }
@@ -142,45 +160,92 @@ __device__ __forceinline__ void load_coefs(const GridView &g, long long off, flo
     }
 }
 
-// Nest S for one wave: row j, i-points ts + lane*VEC .. +VEC-1, planes k0..k1-1.
+// Nest S for one wave: i-points ts + lane*VEC .. +VEC-1 of one line of the
+// grid, marching along it. Without OFL_TILE_MARCH_J the wave owns row j =
+// `fixed` and marches through planes k = m0..m1-1 (consecutive steps one plane
+// apart); with it the wave owns plane k = `fixed` and marches through rows
+// j = m0..m1-1 (consecutive steps one row apart, so every stream the wave reads
+// advances through contiguous memory). Either way rows j-1..j+1 of planes
+// k-1..k+1 stay in registers and each step loads only the three new rows.
 template <int VEC, bool BF16, int FLAGS>
-__device__ __forceinline__ void sweep_march(const GridView &g, int ts, int j, int k0, int k1, float omega) {
+__device__ __forceinline__ void sweep_march(const GridView &g, int ts, int fixed, int m0, int m1, float omega) {
     constexpr bool kNtLoads = (FLAGS & OFL_TILE_NT_LOADS) != 0;
     constexpr bool kNtStores = (FLAGS & OFL_TILE_NT_STORES) != 0;
     constexpr bool kPrefetch = (FLAGS & OFL_TILE_PREFETCH) != 0;
+    constexpr bool kMarchJ = (FLAGS & OFL_TILE_MARCH_J) != 0;
     const int lane = threadIdx.x & (kWave - 1);
     const int ib = ts + lane * VEC;
     const long long pitch = g.pitch;
     const long long plane = g.plane;
     const float *__restrict__ p = g.p;
+    auto row = [&](int j, int k) { return p + j * pitch + k * plane; };
+    // offset of the coefficients of step m, and of the step after it
+    auto coef_off = [&](int m) {
+        return kMarchJ ? m * pitch + fixed * plane + ib : fixed * pitch + m * plane + ib;
+    };
 
     // P[r][q][e]: row j-1+r, plane k-1+q, element e. EL/ER: outer neighbours.
     float P[3][3][VEC];
     float EL[3][3], ER[3][3];
+    {
+        // the two lines behind the first step
+        float h[2][3];
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int r = 0; r < 3; ++r)
-            load_prow<VEC>(p + (j - 1 + r) * pitch + (k0 - 1 + q) * plane, ib, ts, lane, P[r][q], EL[r][q],
-                           ER[r][q]);
+            for (int b = 0; b < 3; ++b) {
+                if constexpr (kMarchJ)
+                    issue_prow<VEC>(row(m0 - 1 + a, fixed - 1 + b), ib, ts, lane, P[a][b], h[a][b]);
+                else
+                    issue_prow<VEC>(row(fixed - 1 + b, m0 - 1 + a), ib, ts, lane, P[b][a], h[a][b]);
+            }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                if constexpr (kMarchJ)
+                    finish_prow<VEC>(P[a][b], h[a][b], lane, EL[a][b], ER[a][b]);
+                else
+                    finish_prow<VEC>(P[b][a], h[a][b], lane, EL[b][a], ER[b][a]);
+            }
+    }
 
     float C[kNCoef][VEC];
     if constexpr (kPrefetch)
-        load_coefs<VEC, BF16, kNtLoads>(g, j * pitch + k0 * plane + ib, C);
+        load_coefs<VEC, BF16, kNtLoads>(g, coef_off(m0), C);
 
     const int I = g.I;
     float *__restrict__ wrk2 = g.wrk2;
-    for (int k = k0; k < k1; ++k) {
+    for (int m = m0; m < m1; ++m) {
+        const int j = kMarchJ ? m : fixed;
+        const int k = kMarchJ ? fixed : m;
         float Cn[kNCoef][VEC];
         if constexpr (kPrefetch) {
-            if (k + 1 < k1)
-                load_coefs<VEC, BF16, kNtLoads>(g, j * pitch + (k + 1) * plane + ib, Cn);
+            if (m + 1 < m1)
+                load_coefs<VEC, BF16, kNtLoads>(g, coef_off(m + 1), Cn);
         } else {
-            load_coefs<VEC, BF16, kNtLoads>(g, j * pitch + k * plane + ib, C);
+            load_coefs<VEC, BF16, kNtLoads>(g, coef_off(m), C);
         }
+        // the three new rows: j+1 of planes k-1..k+1 (j-march) or
+        // j-1..j+1 of plane k+1 (k-march)
+        float h[3];
 #pragma unroll
-        for (int r = 0; r < 3; ++r)
-            load_prow<VEC>(p + (j - 1 + r) * pitch + (k + 1) * plane, ib, ts, lane, P[r][2], EL[r][2], ER[r][2]);
+        for (int b = 0; b < 3; ++b) {
+            if constexpr (kMarchJ)
+                issue_prow<VEC>(row(j + 1, k - 1 + b), ib, ts, lane, P[2][b], h[b]);
+            else
+                issue_prow<VEC>(row(j - 1 + b, k + 1), ib, ts, lane, P[b][2], h[b]);
+        }
+        // Keep every load of the step ahead of the first use, so one wait
+        // covers them all instead of the scheduler trading them for registers.
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            if constexpr (kMarchJ)
+                finish_prow<VEC>(P[2][b], h[b], lane, EL[2][b], ER[2][b]);
+            else
+                finish_prow<VEC>(P[b][2], h[b], lane, EL[b][2], ER[b][2]);
+        }
 
         float out[VEC];
 #pragma unroll
@@ -207,17 +272,30 @@ __device__ __forceinline__ void sweep_march(const GridView &g, int ts, int j, in
                     w[e] = out[e];
         }
 
+        // slide the register window one step along the march axis
 #pragma unroll
-        for (int r = 0; r < 3; ++r) {
+        for (int b = 0; b < 3; ++b) {
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
-                P[r][0][e] = P[r][1][e];
-                P[r][1][e] = P[r][2][e];
+                if constexpr (kMarchJ) {
+                    P[0][b][e] = P[1][b][e];
+                    P[1][b][e] = P[2][b][e];
+                } else {
+                    P[b][0][e] = P[b][1][e];
+                    P[b][1][e] = P[b][2][e];
+                }
             }
-            EL[r][0] = EL[r][1];
-            EL[r][1] = EL[r][2];
-            ER[r][0] = ER[r][1];
-            ER[r][1] = ER[r][2];
+            if constexpr (kMarchJ) {
+                EL[0][b] = EL[1][b];
+                EL[1][b] = EL[2][b];
+                ER[0][b] = ER[1][b];
+                ER[1][b] = ER[2][b];
+            } else {
+                EL[b][0] = EL[b][1];
+                EL[b][1] = EL[b][2];
+                ER[b][0] = ER[b][1];
+                ER[b][1] = ER[b][2];
+            }
         }
         if constexpr (kPrefetch) {
 #pragma unroll
@@ -229,37 +307,51 @@ __device__ __forceinline__ void sweep_march(const GridView &g, int ts, int j, in
     }
 }
 
+// Lines a wave may own and the extent of its march, per march axis.
+template <int FLAGS>
+__device__ __forceinline__ void march_extent(const GridView &g, int &fixed_last, int &march_end) {
+    constexpr bool kMarchJ = (FLAGS & OFL_TILE_MARCH_J) != 0;
+    fixed_last = kMarchJ ? g.K - 2 : g.J - 2;
+    march_end = kMarchJ ? g.J - 1 : g.K - 1;
+}
+
 template <int VEC, bool BF16, int FLAGS>
-__global__ __launch_bounds__(512) void sweep_kernel(GridView g, int kchunk, int nti, int njb, float omega) {
-    const int L = xcd_remap(blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(512) void sweep_kernel(GridView g, int chunk, int nti, int nfb, float omega,
+                                                    int remap) {
+    const int L = remap ? xcd_remap(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x);
     const int it = L % nti;
     const int rest = L / nti;
-    const int jb = rest % njb;
-    const int kc = rest / njb;
-    const int rows = blockDim.x / kWave;
-    const int j = 1 + jb * rows + static_cast<int>(threadIdx.x / kWave);
-    if (j > g.J - 2)
+    const int fb = rest % nfb;
+    const int mc = rest / nfb;
+    const int lines = blockDim.x / kWave;
+    const int fixed = 1 + fb * lines + static_cast<int>(threadIdx.x / kWave);
+    int fixed_last, march_end;
+    march_extent<FLAGS>(g, fixed_last, march_end);
+    if (fixed > fixed_last)
         return;
-    const int k0 = 1 + kc * kchunk;
-    const int k1 = min(k0 + kchunk, g.K - 1);
-    sweep_march<VEC, BF16, FLAGS>(g, it * kWave * VEC, j, k0, k1, omega);
+    const int m0 = 1 + mc * chunk;
+    const int m1 = min(m0 + chunk, march_end);
+    sweep_march<VEC, BF16, FLAGS>(g, it * kWave * VEC, fixed, m0, m1, omega);
 }
 
 template <int VEC, bool BF16, int FLAGS>
 __global__ __launch_bounds__(512) void batch_sweep_kernel(const GridView *__restrict__ views,
                                                           const SweepItem *__restrict__ items, int nitems,
-                                                          int kchunk, float omega) {
-    const int rows = blockDim.x / kWave;
+                                                          int chunk, float omega, int remap) {
+    const int lines = blockDim.x / kWave;
     const int wave = static_cast<int>(threadIdx.x / kWave);
-    for (int w = xcd_remap(blockIdx.x, gridDim.x); w < nitems; w += gridDim.x) {
+    const int first = remap ? xcd_remap(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x);
+    for (int w = first; w < nitems; w += gridDim.x) {
         const SweepItem item = items[w];
         const GridView g = views[item.grid];
-        const int j = 1 + item.jblock * rows + wave;
-        if (j > g.J - 2)
+        const int fixed = 1 + item.fblock * lines + wave;
+        int fixed_last, march_end;
+        march_extent<FLAGS>(g, fixed_last, march_end);
+        if (fixed > fixed_last)
             continue;
-        const int k0 = 1 + item.kchunk * kchunk;
-        const int k1 = min(k0 + kchunk, g.K - 1);
-        sweep_march<VEC, BF16, FLAGS>(g, item.itile * kWave * VEC, j, k0, k1, omega);
+        const int m0 = 1 + item.mchunk * chunk;
+        const int m1 = min(m0 + chunk, march_end);
+        sweep_march<VEC, BF16, FLAGS>(g, item.itile * kWave * VEC, fixed, m0, m1, omega);
     }
 }
 
@@ -307,30 +399,32 @@ __device__ __forceinline__ long long row_tile_offset(const GridView &g, int rt, 
     return j * static_cast<long long>(g.pitch) + k * g.plane + ib;
 }
 
-// Sum of squared differences over row tiles [first, first + count) for one wave.
-template <int VEC, int SUM>
+// Sum of squared differences over row tiles [first, first + count) for one
+// wave. The unrolled loads are unconditional (past-the-end slots reload the
+// last row tile and are not counted), so all of them are in flight at once.
+template <int VEC, int SUM, bool NT>
 __device__ __forceinline__ void residual_rows(const GridView &g, int first, int count, Acc &acc) {
     const int lane = threadIdx.x & (kWave - 1);
     const int nti = itiles(g.I, VEC);
     const int I = g.I;
-    for (int r0 = first; r0 < first + count; r0 += kRowUnroll) {
+    const int last = first + count - 1;
+    for (int r0 = first; r0 <= last; r0 += kRowUnroll) {
         float pv[kRowUnroll][VEC], wv[kRowUnroll][VEC];
         int ib[kRowUnroll];
 #pragma unroll
         for (int u = 0; u < kRowUnroll; ++u) {
-            ib[u] = 1 << 30;
-            if (r0 + u < first + count) {
-                const long long off = row_tile_offset<VEC>(g, r0 + u, nti, lane, ib[u]);
-                load_f32<VEC, false>(g.p + off, pv[u]);
-                load_f32<VEC, false>(g.wrk2 + off, wv[u]);
-            }
+            const long long off = row_tile_offset<VEC>(g, min(r0 + u, last), nti, lane, ib[u]);
+            load_f32<VEC, NT>(g.p + off, pv[u]);
+            load_f32<VEC, NT>(g.wrk2 + off, wv[u]);
         }
 #pragma unroll
         for (int u = 0; u < kRowUnroll; ++u)
+            if (r0 + u <= last) {
 #pragma unroll
-            for (int e = 0; e < VEC; ++e)
-                if (ib[u] + e >= 1 && ib[u] + e <= I - 2)
-                    acc_add<SUM>(acc, wv[u][e] - pv[u][e]);
+                for (int e = 0; e < VEC; ++e)
+                    if (ib[u] + e >= 1 && ib[u] + e <= I - 2)
+                        acc_add<SUM>(acc, wv[u][e] - pv[u][e]);
+            }
     }
 }
 
@@ -351,19 +445,19 @@ __device__ __forceinline__ double block_sum(double v) {
     return t;
 }
 
-template <int VEC, int SUM>
+template <int VEC, int SUM, bool NT>
 __global__ __launch_bounds__(kResidualThreads) void residual_kernel(GridView g, int rows_per_wave, int nrt) {
     const int wave = blockIdx.x * (kResidualThreads / kWave) + static_cast<int>(threadIdx.x / kWave);
     const int first = wave * rows_per_wave;
     const int count = max(0, min(rows_per_wave, nrt - first));
     Acc acc = {0.0, 0.f, 0.f};
-    residual_rows<VEC, SUM>(g, first, count, acc);
+    residual_rows<VEC, SUM, NT>(g, first, count, acc);
     const double t = block_sum(acc_value<SUM>(acc));
     if (threadIdx.x == 0)
         g.partials[blockIdx.x] = t;
 }
 
-template <int VEC, int SUM>
+template <int VEC, int SUM, bool NT>
 __global__ __launch_bounds__(kResidualThreads) void batch_residual_kernel(const GridView *__restrict__ views,
                                                                           const RowItem *__restrict__ items,
                                                                           int nitems) {
@@ -376,7 +470,7 @@ __global__ __launch_bounds__(kResidualThreads) void batch_residual_kernel(const 
         const int first = item.first + wave * per;
         const int count = max(0, min(per, item.first + item.count - first));
         Acc acc = {0.0, 0.f, 0.f};
-        residual_rows<VEC, SUM>(g, first, count, acc);
+        residual_rows<VEC, SUM, NT>(g, first, count, acc);
         const double t = block_sum(acc_value<SUM>(acc));
         if (threadIdx.x == 0)
             views[item.grid].partials[item.partial] = t;
@@ -417,28 +511,27 @@ __global__ __launch_bounds__(kResidualThreads) void batch_finalize_kernel(const 
 
 // ---------------------------------------------------------------- copy-back
 
-template <int VEC>
+template <int VEC, bool NTL, bool NTS>
 __device__ __forceinline__ void copyback_rows(const GridView &g, int first, int count) {
     const int lane = threadIdx.x & (kWave - 1);
     const int nti = itiles(g.I, VEC);
     const int I = g.I;
-    for (int r0 = first; r0 < first + count; r0 += kRowUnroll) {
+    const int last = first + count - 1;
+    for (int r0 = first; r0 <= last; r0 += kRowUnroll) {
         float wv[kRowUnroll][VEC];
         long long off[kRowUnroll];
         int ib[kRowUnroll];
 #pragma unroll
         for (int u = 0; u < kRowUnroll; ++u) {
-            ib[u] = 1 << 30;
-            off[u] = 0;
-            if (r0 + u < first + count) {
-                off[u] = row_tile_offset<VEC>(g, r0 + u, nti, lane, ib[u]);
-                load_f32<VEC, false>(g.wrk2 + off[u], wv[u]);
-            }
+            off[u] = row_tile_offset<VEC>(g, min(r0 + u, last), nti, lane, ib[u]);
+            load_f32<VEC, NTL>(g.wrk2 + off[u], wv[u]);
         }
 #pragma unroll
         for (int u = 0; u < kRowUnroll; ++u) {
+            if (r0 + u > last)
+                continue;
             if (ib[u] >= 1 && ib[u] + VEC - 1 <= I - 2) {
-                store_f32<VEC, false>(g.p + off[u], wv[u]);
+                store_f32<VEC, NTS>(g.p + off[u], wv[u]);
             } else {
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)
@@ -449,15 +542,15 @@ __device__ __forceinline__ void copyback_rows(const GridView &g, int first, int 
     }
 }
 
-template <int VEC>
+template <int VEC, bool NTL, bool NTS>
 __global__ __launch_bounds__(kResidualThreads) void copyback_kernel(GridView g, int rows_per_wave, int nrt) {
     const int wave = blockIdx.x * (kResidualThreads / kWave) + static_cast<int>(threadIdx.x / kWave);
     const int first = wave * rows_per_wave;
     const int count = max(0, min(rows_per_wave, nrt - first));
-    copyback_rows<VEC>(g, first, count);
+    copyback_rows<VEC, NTL, NTS>(g, first, count);
 }
 
-template <int VEC>
+template <int VEC, bool NTL, bool NTS>
 __global__ __launch_bounds__(kResidualThreads) void batch_copyback_kernel(const GridView *__restrict__ views,
                                                                           const RowItem *__restrict__ items,
                                                                           int nitems) {
@@ -469,7 +562,7 @@ __global__ __launch_bounds__(kResidualThreads) void batch_copyback_kernel(const 
         const int per = (item.count + kWaves - 1) / kWaves;
         const int first = item.first + wave * per;
         const int count = max(0, min(per, item.first + item.count - first));
-        copyback_rows<VEC>(g, first, count);
+        copyback_rows<VEC, NTL, NTS>(g, first, count);
     }
 }
 
@@ -537,51 +630,79 @@ void check_launch(const char *what) { hip_check(hipGetLastError(), what); }
 
 // ------------------------------------------------------------------ launchers
 
-#define OFL_SWEEP_FLAGS(VEC, BF, KERNEL, ...)                                                   \
-    switch (t.flags & 7) {                                                                      \
-    case 0: KERNEL<VEC, BF, 0><<<__VA_ARGS__>>>(ARGS); break;                                   \
-    case 1: KERNEL<VEC, BF, 1><<<__VA_ARGS__>>>(ARGS); break;                                   \
-    case 2: KERNEL<VEC, BF, 2><<<__VA_ARGS__>>>(ARGS); break;                                   \
-    case 3: KERNEL<VEC, BF, 3><<<__VA_ARGS__>>>(ARGS); break;                                   \
-    case 4: KERNEL<VEC, BF, 4><<<__VA_ARGS__>>>(ARGS); break;                                   \
-    case 5: KERNEL<VEC, BF, 5><<<__VA_ARGS__>>>(ARGS); break;                                   \
-    case 6: KERNEL<VEC, BF, 6><<<__VA_ARGS__>>>(ARGS); break;                                   \
-    default: KERNEL<VEC, BF, 7><<<__VA_ARGS__>>>(ARGS); break;                                  \
-    }
+namespace {
 
-#define OFL_SWEEP_DISPATCH(KERNEL, ...)                                                         \
-    if (bf16) {                                                                                 \
-        if (t.vec == 1) { OFL_SWEEP_FLAGS(1, true, KERNEL, __VA_ARGS__) }                       \
-        else if (t.vec == 2) { OFL_SWEEP_FLAGS(2, true, KERNEL, __VA_ARGS__) }                  \
-        else { OFL_SWEEP_FLAGS(4, true, KERNEL, __VA_ARGS__) }                                  \
-    } else {                                                                                    \
-        if (t.vec == 1) { OFL_SWEEP_FLAGS(1, false, KERNEL, __VA_ARGS__) }                      \
-        else if (t.vec == 2) { OFL_SWEEP_FLAGS(2, false, KERNEL, __VA_ARGS__) }                 \
-        else { OFL_SWEEP_FLAGS(4, false, KERNEL, __VA_ARGS__) }                                 \
-    }
+// Launcher tables over (vec, format, flags): one instantiation per combination.
+using SweepLaunch = void (*)(const GridView &, const TileCfg &, float, int, int, int, int, hipStream_t);
+using BatchSweepLaunch = void (*)(const GridView *, const SweepItem *, int, const TileCfg &, float, int,
+                                  hipStream_t);
+
+template <int VEC, bool BF16, int FLAGS>
+void sweep_one(const GridView &g, const TileCfg &t, float omega, int nti, int nfb, int blocks, int, hipStream_t s) {
+    sweep_kernel<VEC, BF16, FLAGS><<<blocks, kWave * t.rows, 0, s>>>(g, t.kchunk, nti, nfb, omega,
+                                                                      (t.flags & OFL_TILE_XCD_REMAP) ? 1 : 0);
+}
+
+template <int VEC, bool BF16, int FLAGS>
+void batch_sweep_one(const GridView *views, const SweepItem *items, int nitems, const TileCfg &t, float omega,
+                     int blocks, hipStream_t s) {
+    batch_sweep_kernel<VEC, BF16, FLAGS><<<blocks, kWave * t.rows, 0, s>>>(views, items, nitems, t.kchunk, omega,
+                                                                            (t.flags & OFL_TILE_XCD_REMAP) ? 1 : 0);
+}
+
+template <int VEC, bool BF16, int... F>
+constexpr std::array<SweepLaunch, sizeof...(F)> sweep_row(std::integer_sequence<int, F...>) {
+    return {&sweep_one<VEC, BF16, F>...};
+}
+
+template <int VEC, bool BF16, int... F>
+constexpr std::array<BatchSweepLaunch, sizeof...(F)> batch_sweep_row(std::integer_sequence<int, F...>) {
+    return {&batch_sweep_one<VEC, BF16, F>...};
+}
+
+constexpr int kFlagCombos = 16;
+using FlagSeq = std::make_integer_sequence<int, kFlagCombos>;
+
+int vec_index(int vec) { return vec == 1 ? 0 : (vec == 2 ? 1 : 2); }
+
+SweepLaunch sweep_launcher(int vec, bool bf16, int flags) {
+    static const std::array<SweepLaunch, kFlagCombos> table[2][3] = {
+        {sweep_row<1, false>(FlagSeq{}), sweep_row<2, false>(FlagSeq{}), sweep_row<4, false>(FlagSeq{})},
+        {sweep_row<1, true>(FlagSeq{}), sweep_row<2, true>(FlagSeq{}), sweep_row<4, true>(FlagSeq{})}};
+    return table[bf16 ? 1 : 0][vec_index(vec)][flags & (kFlagCombos - 1)];
+}
+
+BatchSweepLaunch batch_sweep_launcher(int vec, bool bf16, int flags) {
+    static const std::array<BatchSweepLaunch, kFlagCombos> table[2][3] = {
+        {batch_sweep_row<1, false>(FlagSeq{}), batch_sweep_row<2, false>(FlagSeq{}),
+         batch_sweep_row<4, false>(FlagSeq{})},
+        {batch_sweep_row<1, true>(FlagSeq{}), batch_sweep_row<2, true>(FlagSeq{}),
+         batch_sweep_row<4, true>(FlagSeq{})}};
+    return table[bf16 ? 1 : 0][vec_index(vec)][flags & (kFlagCombos - 1)];
+}
+
+}  // namespace
+
+void sweep_shape(int I, int J, int K, const TileCfg &t, int *nti, int *nfb, int *nmc) {
+    const bool march_j = (t.flags & OFL_TILE_MARCH_J) != 0;
+    *nti = itiles(I, t.vec);
+    *nfb = ((march_j ? K : J) - 2 + t.rows - 1) / t.rows;
+    *nmc = ((march_j ? J : K) - 2 + t.kchunk - 1) / t.kchunk;
+}
 
 void launch_sweep(const GridView &g, const TileCfg &t, int bf16, float omega, hipStream_t s) {
-    const int nti = itiles(g.I, t.vec);
-    const int njb = (g.J - 2 + t.rows - 1) / t.rows;
-    const int nkc = (g.K - 2 + t.kchunk - 1) / t.kchunk;
-    const long long blocks = static_cast<long long>(nti) * njb * nkc;
+    int nti, nfb, nmc;
+    sweep_shape(g.I, g.J, g.K, t, &nti, &nfb, &nmc);
+    const long long blocks = static_cast<long long>(nti) * nfb * nmc;
     if (blocks > 0x7fffffffLL)
         fail(OFL_EINVAL, "sweep launch too large for this tile");
-    const dim3 grid(static_cast<unsigned>(blocks));
-    const dim3 block(kWave * t.rows);
-#define ARGS g, t.kchunk, nti, njb, omega
-    OFL_SWEEP_DISPATCH(sweep_kernel, grid, block, 0, s)
-#undef ARGS
+    sweep_launcher(t.vec, bf16 != 0, t.flags)(g, t, omega, nti, nfb, static_cast<int>(blocks), 0, s);
     check_launch("sweep kernel launch");
 }
 
 void launch_batch_sweep(const GridView *views, const SweepItem *items, int nitems, const TileCfg &t, int bf16,
                         float omega, int grid_blocks, hipStream_t s) {
-    const dim3 grid(static_cast<unsigned>(grid_blocks));
-    const dim3 block(kWave * t.rows);
-#define ARGS views, items, nitems, t.kchunk, omega
-    OFL_SWEEP_DISPATCH(batch_sweep_kernel, grid, block, 0, s)
-#undef ARGS
+    batch_sweep_launcher(t.vec, bf16 != 0, t.flags)(views, items, nitems, t, omega, grid_blocks, s);
     check_launch("batched sweep kernel launch");
 }
 
@@ -591,46 +712,89 @@ static int rows_per_wave(int nrt, int blocks) {
     return static_cast<int>(per < 1 ? 1 : per);
 }
 
-void launch_residual(const GridView &g, int vec, int sum_mode, float omega, hipStream_t s) {
+namespace {
+
+// Dispatch helpers for the residual and copy-back kernels: vec, sum mode and
+// the non-temporal choices are template parameters.
+template <template <int, int, bool> class K, class... A>
+void by_vec_sum_nt(int vec, int sum_mode, bool nt, A &&...a) {
+    auto go = [&](auto v, auto sm, auto n) { K<decltype(v)::value, decltype(sm)::value, decltype(n)::value>::run(a...); };
+    using F64 = std::integral_constant<int, OFL_SUM_F64>;
+    using K32 = std::integral_constant<int, OFL_SUM_KAHAN_F32>;
+    auto with_nt = [&](auto v, auto sm) {
+        if (nt)
+            go(v, sm, std::true_type{});
+        else
+            go(v, sm, std::false_type{});
+    };
+    auto with_sum = [&](auto v) {
+        if (sum_mode == OFL_SUM_F64)
+            with_nt(v, F64{});
+        else
+            with_nt(v, K32{});
+    };
+    if (vec == 1)
+        with_sum(std::integral_constant<int, 1>{});
+    else if (vec == 2)
+        with_sum(std::integral_constant<int, 2>{});
+    else
+        with_sum(std::integral_constant<int, 4>{});
+}
+
+template <int VEC, int SUM, bool NT>
+struct ResidualLaunch {
+    static void run(dim3 grid, dim3 block, hipStream_t s, const GridView &g, int rpw, int nrt) {
+        residual_kernel<VEC, SUM, NT><<<grid, block, 0, s>>>(g, rpw, nrt);
+    }
+};
+
+template <int VEC, int SUM, bool NT>
+struct BatchResidualLaunch {
+    static void run(dim3 grid, dim3 block, hipStream_t s, const GridView *views, const RowItem *items, int n) {
+        batch_residual_kernel<VEC, SUM, NT><<<grid, block, 0, s>>>(views, items, n);
+    }
+};
+
+// copy-back: the "sum mode" slot carries the non-temporal store choice
+template <int VEC, int NTS, bool NTL>
+struct CopybackLaunch {
+    static void run(dim3 grid, dim3 block, hipStream_t s, const GridView &g, int rpw, int nrt) {
+        copyback_kernel<VEC, NTL, NTS != 0><<<grid, block, 0, s>>>(g, rpw, nrt);
+    }
+};
+
+template <int VEC, int NTS, bool NTL>
+struct BatchCopybackLaunch {
+    static void run(dim3 grid, dim3 block, hipStream_t s, const GridView *views, const RowItem *items, int n) {
+        batch_copyback_kernel<VEC, NTL, NTS != 0><<<grid, block, 0, s>>>(views, items, n);
+    }
+};
+
+}  // namespace
+
+void launch_residual(const GridView &g, int vec, int sum_mode, int flags, float omega, hipStream_t s) {
     const int nrt = itiles(g.I, vec) * (g.J - 2) * (g.K - 2);
     const int rpw = rows_per_wave(nrt, kResidualBlocks);
-    const dim3 grid(kResidualBlocks), block(kResidualThreads);
-#define RES(V, S) residual_kernel<V, S><<<grid, block, 0, s>>>(g, rpw, nrt)
-    if (sum_mode == OFL_SUM_F64) {
-        if (vec == 1) RES(1, OFL_SUM_F64); else if (vec == 2) RES(2, OFL_SUM_F64); else RES(4, OFL_SUM_F64);
-    } else {
-        if (vec == 1) RES(1, OFL_SUM_KAHAN_F32); else if (vec == 2) RES(2, OFL_SUM_KAHAN_F32); else RES(4, OFL_SUM_KAHAN_F32);
-    }
-#undef RES
+    by_vec_sum_nt<ResidualLaunch>(vec, sum_mode, (flags & OFL_TILE_NT_LOADS) != 0, dim3(kResidualBlocks),
+                                  dim3(kResidualThreads), s, g, rpw, nrt);
     check_launch("residual kernel launch");
     finalize_kernel<<<1, kResidualThreads, 0, s>>>(g.partials, kResidualBlocks, static_cast<double>(omega), g.gosa);
     check_launch("residual finalize launch");
 }
 
-void launch_copyback(const GridView &g, int vec, hipStream_t s) {
+void launch_copyback(const GridView &g, int vec, int flags, hipStream_t s) {
     const int nrt = itiles(g.I, vec) * (g.J - 2) * (g.K - 2);
     const int blocks = grid_for(nrt, (kResidualThreads / kWave) * kRowUnroll * 2, kResidualBlocks * 4);
     const int rpw = rows_per_wave(nrt, blocks);
-    const dim3 grid(blocks), block(kResidualThreads);
-    if (vec == 1)
-        copyback_kernel<1><<<grid, block, 0, s>>>(g, rpw, nrt);
-    else if (vec == 2)
-        copyback_kernel<2><<<grid, block, 0, s>>>(g, rpw, nrt);
-    else
-        copyback_kernel<4><<<grid, block, 0, s>>>(g, rpw, nrt);
+    by_vec_sum_nt<CopybackLaunch>(vec, (flags & OFL_TILE_NT_STORES) ? 1 : 0, (flags & OFL_TILE_NT_LOADS) != 0,
+                                  dim3(blocks), dim3(kResidualThreads), s, g, rpw, nrt);
     check_launch("copy-back kernel launch");
 }
 
-void launch_batch_residual(const GridView *views, const RowItem *items, int nitems, int vec, int sum_mode,
+void launch_batch_residual(const GridView *views, const RowItem *items, int nitems, int vec, int sum_mode, int flags,
                            int grid_blocks, hipStream_t s) {
-    const dim3 grid(grid_blocks), block(kResidualThreads);
-#define RES(V, S) batch_residual_kernel<V, S><<<grid, block, 0, s>>>(views, items, nitems)
-    if (sum_mode == OFL_SUM_F64) {
-        if (vec == 1) RES(1, OFL_SUM_F64); else if (vec == 2) RES(2, OFL_SUM_F64); else RES(4, OFL_SUM_F64);
-    } else {
-        if (vec == 1) RES(1, OFL_SUM_KAHAN_F32); else if (vec == 2) RES(2, OFL_SUM_KAHAN_F32); else RES(4, OFL_SUM_KAHAN_F32);
-    }
-#undef RES
+    by_vec_sum_nt<BatchResidualLaunch>(vec, sum_mode, (flags & OFL_TILE_NT_LOADS) != 0, dim3(grid_blocks),
+                                       dim3(kResidualThreads), s, views, items, nitems);
     check_launch("batched residual kernel launch");
 }
 
@@ -639,15 +803,10 @@ void launch_batch_finalize(const GridView *views, const int *partial_range, int 
     check_launch("batched finalize launch");
 }
 
-void launch_batch_copyback(const GridView *views, const RowItem *items, int nitems, int vec, int grid_blocks,
-                           hipStream_t s) {
-    const dim3 grid(grid_blocks), block(kResidualThreads);
-    if (vec == 1)
-        batch_copyback_kernel<1><<<grid, block, 0, s>>>(views, items, nitems);
-    else if (vec == 2)
-        batch_copyback_kernel<2><<<grid, block, 0, s>>>(views, items, nitems);
-    else
-        batch_copyback_kernel<4><<<grid, block, 0, s>>>(views, items, nitems);
+void launch_batch_copyback(const GridView *views, const RowItem *items, int nitems, int vec, int flags,
+                           int grid_blocks, hipStream_t s) {
+    by_vec_sum_nt<BatchCopybackLaunch>(vec, (flags & OFL_TILE_NT_STORES) ? 1 : 0, (flags & OFL_TILE_NT_LOADS) != 0,
+                                       dim3(grid_blocks), dim3(kResidualThreads), s, views, items, nitems);
     check_launch("batched copy-back kernel launch");
 }
 

@@ -64,9 +64,10 @@ struct GridView {
     double *gosa;      // device scalar
 };
 
-// Sweep work item (batched launch): grid, i-tile, j-block, k-chunk.
+// Sweep work item (batched launch): grid, i-tile, block of lines a work-group
+// owns (rows j, or planes k when marching along j), chunk of the march.
 struct SweepItem {
-    int grid, itile, jblock, kchunk;
+    int grid, itile, fblock, mchunk;
 };
 // Residual / copy-back work item (batched launch): grid and a range of row tiles.
 struct RowItem {
@@ -83,10 +84,13 @@ ofl_tile to_tile(const TileCfg &c);
 
 __host__ __device__ inline int itiles(int I, int vec) { return (I - 2) / (kWave * vec) + 1; }
 
+// Sweep decomposition of a grid: i-tiles, blocks of owned lines, march chunks.
+void sweep_shape(int I, int J, int K, const TileCfg &t, int *nti, int *nfb, int *nmc);
+
 // Single-grid launches (kernels.hip).
 void launch_sweep(const GridView &g, const TileCfg &t, int bf16, float omega, hipStream_t s);
-void launch_residual(const GridView &g, int vec, int sum_mode, float omega, hipStream_t s);
-void launch_copyback(const GridView &g, int vec, hipStream_t s);
+void launch_residual(const GridView &g, int vec, int sum_mode, int flags, float omega, hipStream_t s);
+void launch_copyback(const GridView &g, int vec, int flags, hipStream_t s);
 void launch_pack(const void *staging, void *arr, int I, int J, int K, int pitch, int elem_bytes, hipStream_t s);
 void launch_unpack(const void *arr, void *staging, int I, int J, int K, int pitch, int elem_bytes, hipStream_t s);
 void launch_fill_zero(void *ptr, size_t bytes, hipStream_t s);
@@ -95,12 +99,12 @@ void launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 // Batched launches (kernels.hip).
 void launch_batch_sweep(const GridView *views, const SweepItem *items, int nitems, const TileCfg &t, int bf16,
                         float omega, int grid_blocks, hipStream_t s);
-void launch_batch_residual(const GridView *views, const RowItem *items, int nitems, int vec, int sum_mode,
+void launch_batch_residual(const GridView *views, const RowItem *items, int nitems, int vec, int sum_mode, int flags,
                            int grid_blocks, hipStream_t s);
 void launch_batch_finalize(const GridView *views, const int *partial_range, int ngrids, float omega,
                            hipStream_t s);
-void launch_batch_copyback(const GridView *views, const RowItem *items, int nitems, int vec, int grid_blocks,
-                           hipStream_t s);
+void launch_batch_copyback(const GridView *views, const RowItem *items, int nitems, int vec, int flags,
+                           int grid_blocks, hipStream_t s);
 
 int device_cu_count(int device);
 

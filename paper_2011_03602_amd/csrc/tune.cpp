@@ -12,8 +12,9 @@
 //   bits 0-1  vec       00:1 01:2 10:4 11: not buildable
 //   bits 2-3  rows      1, 2, 4, 8
 //   bits 4-6  kchunk    4, 8, ..., 512
-//   bits 7-9  flags     OFL_TILE_NT_LOADS | OFL_TILE_NT_STORES | OFL_TILE_PREFETCH
-//   bits 10-11 (batch)  occupancy 0 (one work-group per item), 2, 4, 8 per CU
+//   bits 7-11 flags     OFL_TILE_NT_LOADS | OFL_TILE_NT_STORES | OFL_TILE_PREFETCH |
+//                       OFL_TILE_MARCH_J | OFL_TILE_XCD_REMAP
+//   bits 12-13 (batch)  occupancy 0 (one work-group per item), 2, 4, 8 per CU
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -43,7 +44,7 @@ struct Rng {
     double uniform() { return static_cast<double>(next() >> 11) * 0x1.0p-53; }
 };
 
-int gene_bits(bool batch) { return batch ? 12 : 10; }
+int gene_bits(bool batch) { return batch ? 14 : 12; }
 
 bool decode(uint32_t gene, bool batch, TileCfg *t) {
     const int v = static_cast<int>(gene & 3u);
@@ -52,8 +53,8 @@ bool decode(uint32_t gene, bool batch, TileCfg *t) {
     t->vec = v == 0 ? 1 : (v == 1 ? 2 : 4);
     t->rows = 1 << ((gene >> 2) & 3u);
     t->kchunk = 4 << ((gene >> 4) & 7u);
-    t->flags = static_cast<int>((gene >> 7) & 7u);
-    const int occ = static_cast<int>((gene >> 10) & 3u);
+    t->flags = static_cast<int>((gene >> 7) & 31u);
+    const int occ = static_cast<int>((gene >> 12) & 3u);
     t->occupancy = batch ? (occ == 0 ? 0 : (1 << occ)) : 0;
     return true;
 }
@@ -68,12 +69,12 @@ uint32_t encode(const TileCfg &t, bool batch) {
     while ((4 << k) < t.kchunk && k < 7)
         ++k;
     g |= static_cast<uint32_t>(k) << 4;
-    g |= static_cast<uint32_t>(t.flags & 7) << 7;
+    g |= static_cast<uint32_t>(t.flags & 31) << 7;
     if (batch) {
-        int o = 0;
+        int o = 1;
         while (o < 3 && (1 << o) < t.occupancy)
             ++o;
-        g |= static_cast<uint32_t>(t.occupancy == 0 ? 0 : o) << 10;
+        g |= static_cast<uint32_t>(t.occupancy == 0 ? 0 : o) << 12;
     }
     return g;
 }
@@ -159,9 +160,13 @@ constexpr float kCheckOmega = 0.8f;
 
 // Does the tile reproduce the all-CPU nests on small ragged grids?
 bool tile_correct(const TileCfg &t, bool batch, int fmt, int sum_mode, int device, double tol) {
+    // two i-tiles, two blocks of owned lines and two march chunks, all ragged
+    const bool march_j = (t.flags & OFL_TILE_MARCH_J) != 0;
     const int I = kWave * t.vec + 37;
-    const int J = 2 * t.rows + 3;
-    const int K = std::min(t.kchunk, 24) + 7;
+    const int owned = 2 * t.rows + 3;
+    const int marched = std::min(t.kchunk, 24) + 7;
+    const int J = march_j ? marched : owned;
+    const int K = march_j ? owned : marched;
     std::vector<CheckProblem> probs;
     probs.push_back(make_check(I, J, K, 0xC0FFEEULL + static_cast<uint64_t>(I * 131 + J * 7 + K)));
     if (batch) {
@@ -413,7 +418,7 @@ int ofl_grid_tune(ofl_grid *g, const ofl_ga_params *ga_in, ofl_tune_result *out)
             TileCfg t;
             if (!decode(gene, false, &t))
                 return kInf;
-            const uint32_t key = gene & 0x3ffu;
+            const uint32_t key = gene & 0xfffu;
             auto it = checked.find(key);
             const bool ok = it != checked.end()
                                 ? it->second

@@ -95,6 +95,12 @@ TILES = [
     ofl.tile(vec=4, rows=4, kchunk=32, flags=0),
     ofl.tile(vec=4, rows=5, kchunk=3, flags=7),
     ofl.tile(vec=4, rows=8, kchunk=1024, flags=ofl.OFL_TILE_PREFETCH | ofl.OFL_TILE_NT_LOADS),
+    ofl.tile(vec=4, rows=4, kchunk=4, flags=ofl.OFL_TILE_MARCH_J | ofl.OFL_TILE_NT_LOADS),
+    ofl.tile(vec=2, rows=3, kchunk=5, flags=ofl.OFL_TILE_MARCH_J | ofl.OFL_TILE_PREFETCH),
+    ofl.tile(vec=1, rows=8, kchunk=1, flags=ofl.OFL_TILE_MARCH_J | 7),
+    ofl.tile(vec=4, rows=1, kchunk=64, flags=ofl.OFL_TILE_MARCH_J | ofl.OFL_TILE_NT_STORES),
+    ofl.tile(vec=4, rows=4, kchunk=8, flags=ofl.OFL_TILE_XCD_REMAP | 3),
+    ofl.tile(vec=2, rows=2, kchunk=3, flags=ofl.OFL_TILE_XCD_REMAP | ofl.OFL_TILE_MARCH_J),
 ]
 
 
@@ -117,10 +123,11 @@ def test_tiles(wide, t):
 @pytest.mark.parametrize("dims", [(3, 3, 3), (3, 5, 4), (4, 3, 3), (5, 3, 7), (258, 3, 3), (66, 4, 5), (65, 6, 3),
                                   (130, 3, 4), (257, 5, 4)])
 @pytest.mark.parametrize("vec", [1, 2, 4])
-def test_edge_shapes(dims, vec):
-    say("edge", dims, "vec", vec)
+@pytest.mark.parametrize("march_j", [0, ofl.OFL_TILE_MARCH_J])
+def test_edge_shapes(dims, vec, march_j):
+    say("edge", dims, "vec", vec, "march_j", march_j)
     a = synth.make_problem(*dims, seed=sum(dims))
-    g, gosa = run_gpu(a, 3, tile=ofl.tile(vec=vec, rows=2, kchunk=2))
+    g, gosa = run_gpu(a, 3, tile=ofl.tile(vec=vec, rows=2, kchunk=2, flags=march_j))
     check_against_oracle(a, g, gosa, 3)
     g.close()
 
@@ -306,10 +313,11 @@ def _small_batch(n=6):
 
 @pytest.mark.parametrize("fmt", [ofl.OFL_COEF_F32, ofl.OFL_COEF_BF16_OFFSET])
 @pytest.mark.parametrize("occupancy", [0, 2])
-def test_batch_matches_oracle_and_single_runs(fmt, occupancy):
-    say("batch fmt", fmt, "occupancy", occupancy)
+@pytest.mark.parametrize("march_j", [0, ofl.OFL_TILE_MARCH_J])
+def test_batch_matches_oracle_and_single_runs(fmt, occupancy, march_j):
+    say("batch fmt", fmt, "occupancy", occupancy, "march_j", march_j)
     probs = _small_batch()
-    tile = ofl.tile(vec=2, rows=4, kchunk=16, occupancy=occupancy)
+    tile = ofl.tile(vec=2, rows=4, kchunk=16, occupancy=occupancy, flags=march_j)
     grids = [ofl.Grid(a, coef_format=fmt) for a in probs]
     b = ofl.ofl_batch_create([g.handle for g in grids], tile)
     gosa = ofl.ofl_batch_run(b, 8, OMEGA, len(grids))
@@ -319,7 +327,7 @@ def test_batch_matches_oracle_and_single_runs(fmt, occupancy):
         check_against_oracle(a, g, r, 8, tol_p=tol, tol_g=tol_g)
     # the same tile on one grid at a time: identical per-point arithmetic -> identical p
     for a, g in zip(probs, grids):
-        single, _ = run_gpu(a, 8, tile=ofl.tile(vec=2, rows=4, kchunk=16), fmt=fmt)
+        single, _ = run_gpu(a, 8, tile=ofl.tile(vec=2, rows=4, kchunk=16, flags=march_j), fmt=fmt)
         assert np.array_equal(single.p, g.p)
         single.close()
     ofl.ofl_batch_destroy(b)
