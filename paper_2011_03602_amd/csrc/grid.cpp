@@ -40,7 +40,11 @@ Layout make_layout(int I, int J, int K, int coef_format) {
     L.I = I;
     L.J = J;
     L.K = K;
-    L.pitch = round_up(I, kPitchAlign);
+    // Rows start on 128-byte boundaries for every stored element size: 32
+    // FP32 or 64 bfloat16 elements. (A 576-byte bfloat16 row would start every
+    // other row mid-line, and a wave's 512-byte read would then touch five
+    // cache lines instead of four.)
+    L.pitch = round_up(I, coef_format == OFL_COEF_F32 ? kPitchAlign : 2 * kPitchAlign);
     L.plane = static_cast<size_t>(L.pitch) * J;
     L.elems = L.plane * K;
     L.coef_elem = coef_format == OFL_COEF_F32 ? 4 : 2;

@@ -16,7 +16,7 @@ namespace ofl {
 
 constexpr int kNCoef = 12;
 constexpr int kWave = 64;
-constexpr int kPitchAlign = 32;   // elements: rows start on 128-byte boundaries (FP32)
+constexpr int kPitchAlign = 32;   // FP32 elements per 128 bytes (row alignment of the pitched layout)
 constexpr size_t kGuard = 1024;   // elements of slack before and after every device array
 constexpr int kResidualBlocks = 2048;  // fixed -> deterministic residual partials
 constexpr int kResidualThreads = 256;
