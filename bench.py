@@ -159,6 +159,81 @@ def run_batch(ofl, n_grids, fmt, steps, warmup, tune, iters=ITERS):
     }
 
 
+def run_masks(ofl, steps_unused=None):
+    """Every gene x placement on 129x129x257 for 200 iterations, end to end
+    (transfers included, host arrays in pinned memory), against the all-CPU
+    gene (the original program's loops) and the FP64 oracle."""
+    import torch
+
+    import oracle
+    import synth
+
+    I, J, K, iters = 129, 129, 257, 200
+    arrays = synth.make_problem(I, J, K)
+    log("oracle: 129x129x257 x200")
+    t0 = time.perf_counter()
+    p_ref, g_ref = oracle.jacobi(arrays, iters, float(OMEGA))
+    t_oracle = time.perf_counter() - t0
+    inner = (slice(1, -1),) * 3
+    lups = interior(I, J, K) * iters
+    rows = []
+    for mode, mode_name in ((ofl.OFL_XFER_PER_ITER, "per-iteration"), (ofl.OFL_XFER_HOISTED, "hoisted")):
+        for mask in range(8):
+            g = ofl.Grid(arrays, torch_memory=True, pinned=True)
+            ofl.ofl_set_offload_mask(g.handle, mask, mode)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gosa = ofl.ofl_jacobi_run(g.handle, iters, OMEGA)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            st = ofl.ofl_get_stats(g.handle)
+            err = float(np.max(np.abs(g.p[inner] - p_ref[inner])) / np.max(np.abs(p_ref[inner])))
+            rows.append({"mask": mask, "mask_CRS": format(mask, "03b"), "placement": mode_name, "seconds": round(dt, 4),
+                         "glups": round(lups / dt / 1e9, 4), "h2d": int(st.h2d_count), "d2h": int(st.d2h_count),
+                         "pcie_gb": round((st.h2d_bytes + st.d2h_bytes) / 1e9, 3), "p_rel_err": err,
+                         "gosa_rel_err": abs(gosa - g_ref) / abs(g_ref)})
+            log(f"mask {mask:03b} {mode_name}: {dt:.3f} s")
+            g.close()
+    cpu = {r["placement"]: r["seconds"] for r in rows if r["mask"] == 0}
+    for r in rows:
+        r["speedup_vs_all_cpu_gene"] = round(cpu[r["placement"]] / r["seconds"], 2)
+        r["speedup_vs_oracle"] = round(t_oracle / r["seconds"], 2)
+    return {"config": "129x129x257 FP32, 200 iterations, every gene x placement", "oracle_seconds": round(t_oracle, 3),
+            "host_threads_cpu_nests": os.environ.get("OFL_CPU_THREADS") or os.environ.get("OMP_NUM_THREADS")
+            or os.cpu_count(), "rows": rows}
+
+
+def run_precision(ofl):
+    """Errors of every storage format and residual mode against the FP64
+    oracle on the FP32 inputs, 257x257x513, 100 iterations."""
+    import oracle
+    import synth
+
+    I, J, K = SHAPE
+    arrays = synth.make_problem(I, J, K)
+    log("oracle: 257x257x513 x100 (about a minute)")
+    p_ref, g_ref = oracle.jacobi(arrays, ITERS, float(OMEGA))
+    inner = (slice(1, -1),) * 3
+    ref_inner = p_ref[inner]
+    scale = float(np.max(np.abs(ref_inner)))
+    out = []
+    for fmt, fname in ((ofl.OFL_COEF_F32, "f32"), (ofl.OFL_COEF_BF16, "bf16-plain"),
+                       (ofl.OFL_COEF_BF16_OFFSET, "bf16-offset")):
+        for sm, sname in ((ofl.OFL_SUM_F64, "f64"), (ofl.OFL_SUM_KAHAN_F32, "kahan-f32")):
+            g = ofl.Grid(arrays, coef_format=fmt, sum_mode=sm, torch_memory=True)
+            gosa = ofl.ofl_jacobi_run(g.handle, ITERS, OMEGA)
+            d = g.p[inner].astype(np.float64) - ref_inner
+            out.append({"coef": fname, "residual_sum": sname,
+                        "p_max_abs_err": float(np.max(np.abs(d))),
+                        "p_max_rel_err": float(np.max(np.abs(d)) / scale),
+                        "p_l2_rel_err": float(np.linalg.norm(d) / np.linalg.norm(ref_inner)),
+                        "gosa": gosa, "gosa_rel_err": abs(gosa - g_ref) / abs(g_ref)})
+            log(f"{fname} {sname}: p max rel {out[-1]['p_max_rel_err']:.2e} gosa rel {out[-1]['gosa_rel_err']:.2e}")
+            g.close()
+    return {"config": "257x257x513, 100 iterations, errors vs the FP64 oracle on the FP32 inputs",
+            "gosa_oracle": g_ref, "rows": out}
+
+
 def cpu_baseline(arrays, iters):
     import oracle
 
@@ -192,6 +267,9 @@ def main():
                     help="headline|bf16|batch|copy: run just that under a profiler, print no JSON")
     ap.add_argument("--profile-iters", type=int, default=ITERS,
                     help="iterations per step in --profile-only runs (counter passes use a few)")
+    ap.add_argument("--config", default="headline", choices=["headline", "masks", "precision"],
+                    help="headline: the benchmark line; masks: every gene x placement at 129x129x257; "
+                         "precision: format/residual errors vs the FP64 oracle at 257x257x513")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -208,6 +286,12 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     ofl.lib()  # fail loudly if the library is missing
+    if args.config == "masks":
+        print(json.dumps(run_masks(ofl)), flush=True)
+        return
+    if args.config == "precision":
+        print(json.dumps(run_precision(ofl)), flush=True)
+        return
     if args.profile_only == "copy":
         # Copy kernel of known size: calibrates the HBM byte counters.
         nbytes = 1 << 30

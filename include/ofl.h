@@ -165,7 +165,9 @@ int ofl_grid_coef_bias(const ofl_grid *g, float bias[12]);
                                  instead of round-robin (all XCDs stream one window of HBM) */
 
 typedef struct ofl_tile {
-    int vec;       /* consecutive i-points per lane: 1, 2 or 4 (a wave spans 64*vec points) */
+    int vec;       /* consecutive i-points per lane: 1, 2 or 4 (a wave spans 64*vec points);
+                      batches also accept 0: each grid gets the width that leaves the
+                      fewest idle lanes on its rows (one batched launch per width) */
     int rows;      /* lines per work-group = waves per work-group: 1..8 (j-rows, or k-planes
                       with OFL_TILE_MARCH_J) */
     int kchunk;    /* steps each wave marches through (k-planes, or j-rows with

@@ -61,6 +61,23 @@ void upload(void *&dst, const std::vector<T> &src, hipStream_t s) {
 
 }  // namespace
 
+// Vector width for a grid of I points along i: the one whose wave tiles cover
+// the interior with the fewest idle lanes; wider wins ties within 5%.
+int batch_auto_vec(int I) {
+    const int w = I - 2;
+    int best = 4;
+    double best_util = 0.0;
+    for (int vec : {4, 2, 1}) {
+        const int span = kWave * vec;
+        const double util = static_cast<double>(w) / (span * ((w + span - 1) / span));
+        if (util > best_util * 1.05) {
+            best_util = util;
+            best = vec;
+        }
+    }
+    return best;
+}
+
 void batch_build_tables(ofl_batch *b) {
     if (b->tables_ready)
         return;
@@ -77,27 +94,42 @@ void batch_build_tables(ofl_batch *b) {
     };
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return interior(x) > interior(y); });
 
-    const TileCfg &t = b->tile;
-    std::vector<SweepItem> sitems;
-    std::vector<RowItem> ritems;
+    // Items are grouped by the vector width their grid runs with (one batched
+    // launch per width); with tile.vec == 0 each grid gets the width that
+    // leaves the fewest idle lanes on its interior rows.
+    std::vector<SweepItem> sitems_by[3];
+    std::vector<RowItem> ritems_by[3];
     std::vector<int> range(static_cast<size_t>(n) + 1, 0);
     std::vector<int> count(static_cast<size_t>(n), 0);
     const int rows_per_item = kRowsPerWaveItem * (kResidualThreads / kWave);
     for (int g : order) {
         const ofl_grid *q = b->grids[static_cast<size_t>(g)];
+        TileCfg t = b->tile;
+        t.vec = b->tile.vec > 0 ? b->tile.vec : batch_auto_vec(q->I);
+        const int c = t.vec == 1 ? 0 : (t.vec == 2 ? 1 : 2);
         int nti, nfb, nmc;
         sweep_shape(q->I, q->J, q->K, t, &nti, &nfb, &nmc);
         for (int mc = 0; mc < nmc; ++mc)
             for (int fb = 0; fb < nfb; ++fb)
                 for (int it = 0; it < nti; ++it)
-                    sitems.push_back({g, it, fb, mc});
+                    sitems_by[c].push_back({g, it, fb, mc});
         const int nrt = nti * (q->J - 2) * (q->K - 2);
         int slot = 0;
         for (int first = 0; first < nrt; first += rows_per_item) {
-            ritems.push_back({g, first, std::min(rows_per_item, nrt - first), slot});
+            ritems_by[c].push_back({g, first, std::min(rows_per_item, nrt - first), slot});
             ++slot;
         }
         count[static_cast<size_t>(g)] = slot;
+    }
+    std::vector<SweepItem> sitems;
+    std::vector<RowItem> ritems;
+    for (int c = 0; c < 3; ++c) {
+        b->s_off[c] = static_cast<int>(sitems.size());
+        b->s_cnt[c] = static_cast<int>(sitems_by[c].size());
+        b->r_off[c] = static_cast<int>(ritems.size());
+        b->r_cnt[c] = static_cast<int>(ritems_by[c].size());
+        sitems.insert(sitems.end(), sitems_by[c].begin(), sitems_by[c].end());
+        ritems.insert(ritems.end(), ritems_by[c].begin(), ritems_by[c].end());
     }
     for (int g = 0; g < n; ++g)
         range[static_cast<size_t>(g) + 1] = range[static_cast<size_t>(g)] + count[static_cast<size_t>(g)];
@@ -114,9 +146,20 @@ void batch_build_tables(ofl_batch *b) {
     upload(b->d_ritems, ritems, s);
     upload(b->d_range, range, s);
     hip_check(hipStreamSynchronize(s), "hipStreamSynchronize(batch tables)");
-    b->n_sitems = static_cast<int>(sitems.size());
-    b->n_ritems = static_cast<int>(ritems.size());
     b->tables_ready = true;
+}
+
+namespace {
+
+}  // namespace
+
+// A batch tile may leave the vector width to the batch (vec = 0).
+bool batch_auto_vec_tile(const ofl_tile &t) {
+    ofl_tile u = t;
+    if (u.vec != 0)
+        return false;
+    u.vec = 4;
+    return tile_valid(u, nullptr);
 }
 
 namespace {
@@ -129,21 +172,33 @@ int blocks_for(const ofl_batch *b, int nitems) {
 
 }  // namespace
 
-// Enqueue iters x (S, R, finalize, C) for every grid on the batch stream.
+// Enqueue iters x (S, R, finalize, C) for every grid on the batch stream:
+// per nest one batched launch per vector-width class that has work.
 void batch_enqueue(ofl_batch *b, int iters, float omega) {
     const auto *views = static_cast<const GridView *>(b->d_views);
     const auto *sitems = static_cast<const SweepItem *>(b->d_sitems);
     const auto *ritems = static_cast<const RowItem *>(b->d_ritems);
     const auto *range = static_cast<const int *>(b->d_range);
     const int n = static_cast<int>(b->grids.size());
+    const int vecs[3] = {1, 2, 4};
     for (int it = 0; it < iters; ++it) {
-        launch_batch_sweep(views, sitems, b->n_sitems, b->tile, b->fmt != OFL_COEF_F32, omega,
-                           blocks_for(b, b->n_sitems), b->stream);
-        launch_batch_residual(views, ritems, b->n_ritems, b->tile.vec, b->sum_mode, b->tile.flags,
-                              blocks_for(b, b->n_ritems), b->stream);
+        for (int c = 0; c < 3; ++c) {
+            if (b->s_cnt[c] == 0)
+                continue;
+            TileCfg t = b->tile;
+            t.vec = vecs[c];
+            launch_batch_sweep(views, sitems + b->s_off[c], b->s_cnt[c], t, b->fmt != OFL_COEF_F32, omega,
+                               blocks_for(b, b->s_cnt[c]), b->stream);
+        }
+        for (int c = 0; c < 3; ++c)
+            if (b->r_cnt[c] > 0)
+                launch_batch_residual(views, ritems + b->r_off[c], b->r_cnt[c], vecs[c], b->sum_mode, b->tile.flags,
+                                      blocks_for(b, b->r_cnt[c]), b->stream);
         launch_batch_finalize(views, range, n, omega, b->stream);
-        launch_batch_copyback(views, ritems, b->n_ritems, b->tile.vec, b->tile.flags, blocks_for(b, b->n_ritems),
-                              b->stream);
+        for (int c = 0; c < 3; ++c)
+            if (b->r_cnt[c] > 0)
+                launch_batch_copyback(views, ritems + b->r_off[c], b->r_cnt[c], vecs[c], b->tile.flags,
+                                      blocks_for(b, b->r_cnt[c]), b->stream);
     }
 }
 
@@ -242,7 +297,7 @@ int ofl_batch_create(ofl_grid *const *grids, int n, const ofl_tile *tile, ofl_ba
         if (!grids || !out || n < 1)
             fail(OFL_EINVAL, "grids, out and n >= 1 are required");
         std::string why;
-        if (tile && !tile_valid(*tile, &why))
+        if (tile && !(tile_valid(*tile, &why) || batch_auto_vec_tile(*tile)))
             fail(OFL_EINVAL, why);
         for (int t = 0; t < n; ++t) {
             if (!grids[t])
@@ -262,7 +317,7 @@ int ofl_batch_create(ofl_grid *const *grids, int n, const ofl_tile *tile, ofl_ba
         if (tile) {
             b->tile = to_cfg(*tile);
         } else {
-            b->tile.vec = 2;
+            b->tile.vec = 0;
             b->tile.rows = 4;
             b->tile.kchunk = 4;
             b->tile.flags = OFL_TILE_NT_LOADS;
@@ -293,7 +348,7 @@ int ofl_batch_set_tile(ofl_batch *b, const ofl_tile *tile) {
         if (!b || !tile)
             fail(OFL_EINVAL, "NULL argument");
         std::string why;
-        if (!tile_valid(*tile, &why))
+        if (!tile_valid(*tile, &why) && !batch_auto_vec_tile(*tile))
             fail(OFL_EINVAL, why);
         const TileCfg c = to_cfg(*tile);
         if (c.vec != b->tile.vec || c.rows != b->tile.rows || c.kchunk != b->tile.kchunk ||

@@ -21,8 +21,8 @@ struct ofl_batch {
     void *d_ritems = nullptr;
     void *d_range = nullptr;
     void *d_partials = nullptr;
-    int n_sitems = 0;
-    int n_ritems = 0;
+    int s_off[3] = {}, s_cnt[3] = {};  // sweep items per vector-width class (1, 2, 4)
+    int r_off[3] = {}, r_cnt[3] = {};  // residual/copy-back items per class
 
     hipGraphExec_t exec = nullptr;
     int graph_iters = -1;
@@ -37,5 +37,7 @@ void batch_enqueue(ofl_batch *b, int iters, float omega);
 void batch_launch(ofl_batch *b, int iters, float omega);
 void batch_finish(ofl_batch *b, int iters, double *gosa_out);
 void batch_mark_done(ofl_batch *b, int iters);
+int batch_auto_vec(int I);
+bool batch_auto_vec_tile(const ofl_tile &t);
 
 }  // namespace ofl

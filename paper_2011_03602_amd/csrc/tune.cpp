@@ -15,6 +15,7 @@
 //   bits 7-11 flags     OFL_TILE_NT_LOADS | OFL_TILE_NT_STORES | OFL_TILE_PREFETCH |
 //                       OFL_TILE_MARCH_J | OFL_TILE_XCD_REMAP
 //   bits 12-13 (batch)  occupancy 0 (one work-group per item), 2, 4, 8 per CU
+//   bit 14 (batch)      vector width chosen per grid (overrides bits 0-1)
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -44,7 +45,7 @@ struct Rng {
     double uniform() { return static_cast<double>(next() >> 11) * 0x1.0p-53; }
 };
 
-int gene_bits(bool batch) { return batch ? 14 : 12; }
+int gene_bits(bool batch) { return batch ? 15 : 12; }
 
 bool decode(uint32_t gene, bool batch, TileCfg *t) {
     const int v = static_cast<int>(gene & 3u);
@@ -56,11 +57,15 @@ bool decode(uint32_t gene, bool batch, TileCfg *t) {
     t->flags = static_cast<int>((gene >> 7) & 31u);
     const int occ = static_cast<int>((gene >> 12) & 3u);
     t->occupancy = batch ? (occ == 0 ? 0 : (1 << occ)) : 0;
+    if (batch && ((gene >> 14) & 1u))
+        t->vec = 0;
     return true;
 }
 
 uint32_t encode(const TileCfg &t, bool batch) {
     uint32_t g = t.vec == 1 ? 0u : (t.vec == 2 ? 1u : 2u);
+    if (batch && t.vec == 0)
+        g |= 1u << 14;
     int r = 0;
     while ((1 << r) < t.rows && r < 3)
         ++r;
@@ -162,7 +167,7 @@ constexpr float kCheckOmega = 0.8f;
 bool tile_correct(const TileCfg &t, bool batch, int fmt, int sum_mode, int device, double tol) {
     // two i-tiles, two blocks of owned lines and two march chunks, all ragged
     const bool march_j = (t.flags & OFL_TILE_MARCH_J) != 0;
-    const int I = kWave * t.vec + 37;
+    const int I = kWave * (t.vec > 0 ? t.vec : 4) + 37;
     const int owned = 2 * t.rows + 3;
     const int marched = std::min(t.kchunk, 24) + 7;
     const int J = march_j ? marched : owned;

@@ -335,6 +335,22 @@ def test_batch_matches_oracle_and_single_runs(fmt, occupancy, march_j):
         g.close()
 
 
+@pytest.mark.parametrize("fmt", [ofl.OFL_COEF_F32, ofl.OFL_COEF_BF16_OFFSET])
+def test_batch_per_grid_vector_width(fmt):
+    say("batch vec=0 fmt", fmt)
+    probs = _small_batch()
+    grids = [ofl.Grid(a, coef_format=fmt) for a in probs]
+    b = ofl.ofl_batch_create([g.handle for g in grids], ofl.tile(vec=0, rows=4, kchunk=4, flags=1))
+    gosa = ofl.ofl_batch_run(b, 6, OMEGA, len(grids))
+    tol = TOL_P_F32 if fmt == ofl.OFL_COEF_F32 else TOL_BF16
+    tol_g = TOL_GOSA_F32 if fmt == ofl.OFL_COEF_F32 else TOL_BF16
+    for a, g, r in zip(probs, grids, gosa):
+        check_against_oracle(a, g, r, 6, tol_p=tol, tol_g=tol_g)
+    ofl.ofl_batch_destroy(b)
+    for g in grids:
+        g.close()
+
+
 def test_batch_graph_replays_continue_the_iteration():
     say("batch graph replay")
     probs = _small_batch(4)
