@@ -65,7 +65,7 @@ def measured_traffic():
     return rec.get("hbm_bytes_per_launch")
 
 
-def run_single(ofl, arrays, fmt, steps, warmup, tile=None, profile=True, iters=ITERS):
+def run_single(ofl, arrays, fmt, steps, warmup, tile=None, profile=True, iters=ITERS, fusion=0):
     """Time `steps` runs of ITERS iterations on one grid; returns a result dict."""
     import torch
 
@@ -73,6 +73,8 @@ def run_single(ofl, arrays, fmt, steps, warmup, tile=None, profile=True, iters=I
     h = g.handle
     if tile is not None:
         ofl.ofl_set_tile(h, tile)
+    if fusion:
+        ofl.ofl_set_fusion(h, fusion)
     ofl.ofl_set_offload_mask(h, ofl.OFL_MASK_ALL_GPU, ofl.OFL_XFER_HOISTED)
     ofl.ofl_data_enter(h)  # inputs resident in HBM before timing
     for _ in range(warmup):
@@ -376,10 +378,25 @@ def main():
                 "speedup_vs_f32": round(bf["glups"] / head["glups"], 3),
             }
         }
+        fuse = ofl.OFL_FUSE_RESIDUAL | ofl.OFL_FUSE_COPYBACK_SWAP
+        for name, fmt, ib in (("fused_f32", ofl.OFL_COEF_F32, 56), ("fused_bf16_offset", ofl.OFL_COEF_BF16_OFFSET, 32)):
+            log(f"{name} variant (sweep with the residual folded in, copy-back as a buffer exchange)")
+            fr = run_single(ofl, arrays, fmt, args.steps, args.warmup, fusion=fuse)
+            out["variants"][name] = {
+                "glups": round(fr["glups"], 3),
+                "ms_per_step": round(fr["ms_per_step"], 3),
+                "hbm_gbs_iteration": round(fr["glups"] * ib, 1),
+                "sweep_avg_us": round(fr["nest_ms_avg"][0] * 1e3, 2),
+                "speedup_vs_f32": round(fr["glups"] / head["glups"], 3),
+            }
         if not args.skip_batch:
-            log("batched variant")
+            log("batched variant, FP32")
             bt = run_batch(ofl, args.batch_grids, ofl.OFL_COEF_F32, max(1, args.steps // 2), 1, args.tune_batch)
             out["variants"]["batched_f32"] = bt
+            log("batched variant, bfloat16-offset")
+            bb = run_batch(ofl, args.batch_grids, ofl.OFL_COEF_BF16_OFFSET, max(1, args.steps // 2), 1,
+                           args.tune_batch)
+            out["variants"]["batched_bf16_offset"] = bb
     if not args.skip_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(arrays, args.oracle_iters)
     print(json.dumps(out), flush=True)

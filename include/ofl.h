@@ -152,6 +152,22 @@ int ofl_data_enter(ofl_grid *g);
 int ofl_update_host(ofl_grid *g);
 int ofl_data_exit(ofl_grid *g);
 
+/* ---- fusion of adjacent GPU nests ---------------------------------------- */
+/* Extends the hoisting idea of Sec. 3.2.1 from PCIe to HBM traffic: when every
+ * nest runs on the GPU (gene 111) with hoisted transfers, the sweep can also
+ * produce the residual (OFL_FUSE_RESIDUAL: the residual nest's own terms,
+ * (wrk2 - p) in FP32 squared and summed in FP64, one partial per wave, then a
+ * fixed-order sum), and the copy-back can become an exchange of the p and wrk2
+ * device buffers (OFL_FUSE_COPYBACK_SWAP: exact, because the sweep writes only
+ * the interior and wrk2's device copy first receives p's boundary). Results
+ * equal the unfused path's up to the residual's summation order; wrk2's device
+ * content after a run is unspecified (it is scratch). Other genes, per-iteration
+ * placement and batched runs ignore the setting. EINVAL for unknown bits;
+ * ESTATE while the grid belongs to a batch. */
+#define OFL_FUSE_RESIDUAL 1u
+#define OFL_FUSE_COPYBACK_SWAP 2u
+int ofl_set_fusion(ofl_grid *g, unsigned flags);
+
 /* Per-array FP32 bias of the bfloat16-offset format (zeros for the other
  * formats), in coefficient order. */
 int ofl_grid_coef_bias(const ofl_grid *g, float bias[12]);

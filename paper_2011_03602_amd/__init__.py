@@ -31,6 +31,7 @@ OFL_TILE_NT_LOADS, OFL_TILE_NT_STORES, OFL_TILE_PREFETCH, OFL_TILE_MARCH_J, OFL_
 ARRAY_NAMES = ("a0", "a1", "a2", "a3", "b0", "b1", "b2", "c0", "c1", "c2", "bnd", "wrk1", "p", "wrk2")
 COEF_NAMES = ARRAY_NAMES[:12]
 OFL_ARR_P, OFL_ARR_WRK2 = 12, 13
+OFL_FUSE_RESIDUAL, OFL_FUSE_COPYBACK_SWAP = 1, 2
 
 _FP = ctypes.POINTER(ctypes.c_float)
 
@@ -101,6 +102,7 @@ _SIGS = {
     "ofl_update_host": ([ctypes.c_void_p], ctypes.c_int),
     "ofl_data_exit": ([ctypes.c_void_p], ctypes.c_int),
     "ofl_grid_coef_bias": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+    "ofl_set_fusion": ([ctypes.c_void_p, ctypes.c_uint], ctypes.c_int),
     "ofl_set_tile": ([ctypes.c_void_p, ctypes.POINTER(OflTile)], ctypes.c_int),
     "ofl_get_tile": ([ctypes.c_void_p, ctypes.POINTER(OflTile)], ctypes.c_int),
     "ofl_set_profiling": ([ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
@@ -199,6 +201,10 @@ def ofl_grid_coef_bias(g) -> np.ndarray:
     out = (ctypes.c_float * 12)()
     _check(lib().ofl_grid_coef_bias(g, out))
     return np.array(list(out), dtype=np.float32)
+
+
+def ofl_set_fusion(g, flags: int) -> None:
+    _check(lib().ofl_set_fusion(g, flags))
 
 
 def ofl_set_tile(g, tile: OflTile) -> None:

@@ -309,6 +309,8 @@ int ofl_batch_create(ofl_grid *const *grids, int n, const ofl_tile *tile, ofl_ba
             for (int u = 0; u < t; ++u)
                 if (grids[u] == grids[t])
                     fail(OFL_EINVAL, "a grid appears twice in the batch");
+            if (grids[t]->fusion != 0)
+                fail(OFL_ESTATE, "a grid with fusion enabled cannot join a batch (ofl_set_fusion(g, 0) first)");
         }
         std::unique_ptr<ofl_batch> b(new ofl_batch);
         b->grids.assign(grids, grids + n);

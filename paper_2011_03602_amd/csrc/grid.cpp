@@ -8,6 +8,7 @@
 // 4.2.2).
 #include <algorithm>
 #include <cmath>
+#include <utility>
 #include <cstring>
 #include <limits>
 #include <memory>
@@ -267,8 +268,89 @@ void cpu_nest(ofl_grid *g, int nest, float omega) {
 
 }  // namespace
 
+namespace {
+
+// p and wrk2 exchange device buffers: the copy-back of a fused iteration.
+void swap_p_wrk2(ofl_grid *g) {
+    std::swap(g->lay.off[OFL_ARR_P], g->lay.off[OFL_ARR_WRK2]);
+    std::swap(g->view.p, g->view.wrk2);
+    g->swap_epoch += 1;
+}
+
+// Fused iterations (gene 111, hoisted, fusion requested): the sweep also
+// produces the residual's per-wave partials (OFL_FUSE_RESIDUAL), and the
+// copy-back becomes a buffer exchange (OFL_FUSE_COPYBACK_SWAP), which is exact
+// because the sweep writes only the interior and wrk2's boundary was made
+// equal to p's first. The three nests still count as executed on the GPU.
+void run_fused(ofl_grid *g, int iters, float omega) {
+    grid_ensure_device(g);
+    std::vector<Xfer> xs;
+    const bool fuse_r = (g->fusion & OFL_FUSE_RESIDUAL) != 0;
+    const bool swap = (g->fusion & OFL_FUSE_COPYBACK_SWAP) != 0;
+    if (fuse_r) {
+        const long long need = sweep_waves(g->I, g->J, g->K, g->tile);
+        if (need > g->fused_parts_cap) {
+            grid_sync(g);
+            if (g->fused_parts)
+                hip_check(hipFree(g->fused_parts), "hipFree(fused partials)");
+            g->fused_parts = nullptr;
+            g->fused_parts_cap = 0;
+            void *ptr = nullptr;
+            hip_check(hipMalloc(&ptr, sizeof(double) * static_cast<size_t>(need)), "hipMalloc(fused partials)");
+            g->fused_parts = static_cast<double *>(ptr);
+            g->fused_parts_cap = need;
+        }
+    }
+    for (int it = 0; it < iters; ++it) {
+        xs.clear();
+        plan_before(it, kS, true, OFL_XFER_HOISTED, g->valid, xs);
+        grid_exec(g, xs);
+        if (swap && !g->wrk2_boundary_ok) {
+            // whole-array copy p -> wrk2 once, so both buffers share the boundary
+            const size_t bytes = g->lay.elems * sizeof(float);
+            launch_copy(grid_array_ptr(g, OFL_ARR_WRK2), grid_array_ptr(g, OFL_ARR_P), bytes, g->stream);
+            g->wrk2_boundary_ok = true;
+        }
+        prof_begin(g, kS);
+        launch_sweep(g->view, g->tile, g->fmt != OFL_COEF_F32, omega, g->stream, fuse_r ? g->fused_parts : nullptr);
+        prof_end(g);
+        g->stats.gpu_nests[kS] += 1;
+        xs.clear();
+        plan_after(it, kS, true, OFL_XFER_HOISTED, g->valid, xs);
+        if (fuse_r) {
+            prof_begin(g, kR);
+            launch_finalize(g->fused_parts, sweep_waves(g->I, g->J, g->K, g->tile), omega, g->view.gosa, g->stream,
+                            g->view.partials, kResidualBlocks);
+            prof_end(g);
+        } else {
+            prof_begin(g, kR);
+            launch_residual(g->view, g->tile.vec, g->sum_mode, g->tile.flags, omega, g->stream);
+            prof_end(g);
+        }
+        g->gosa_on_dev = true;
+        g->stats.gpu_nests[kR] += 1;
+        if (swap) {
+            swap_p_wrk2(g);
+        } else {
+            prof_begin(g, kC);
+            launch_copyback(g->view, g->tile.vec, g->tile.flags, g->stream);
+            prof_end(g);
+        }
+        plan_after(it, kC, true, OFL_XFER_HOISTED, g->valid, xs);
+        g->stats.gpu_nests[kC] += 1;
+        g->pending = true;
+    }
+}
+
+}  // namespace
+
 // The outer loop of the offloaded program: iters x (S, R[, C]).
 void grid_run_loop(ofl_grid *g, int iters, float omega, int nests) {
+    if (nests == 3 && g->fusion != 0 && g->mask == OFL_MASK_ALL_GPU && g->mode == OFL_XFER_HOISTED &&
+        g->batch_refs == 0) {
+        run_fused(g, iters, omega);
+        return;
+    }
     std::vector<Xfer> xs;
     for (int it = 0; it < iters; ++it) {
         for (int nest = 0; nest < nests; ++nest) {
@@ -372,6 +454,8 @@ void grid_exec(ofl_grid *g, const std::vector<Xfer> &xs) {
             hip_check(hipMemcpyAsync(staging, host_src(g, x.array), bytes, hipMemcpyHostToDevice, g->stream),
                       "hipMemcpyAsync(host->device)");
             launch_pack(staging, arr, g->I, g->J, g->K, g->lay.pitch, static_cast<int>(eb), g->stream);
+            if (x.array == OFL_ARR_P || x.array == OFL_ARR_WRK2)
+                g->wrk2_boundary_ok = false;
             g->stats.h2d_count += 1;
             g->stats.h2d_bytes += bytes;
         } else {
@@ -460,6 +544,8 @@ void ofl_grid_destroy(ofl_grid *g) {
         (void)hipStreamSynchronize(g->stream);
         for (hipEvent_t e : g->ev)
             (void)hipEventDestroy(e);
+        if (g->fused_parts)
+            (void)hipFree(g->fused_parts);
         if (g->own_block)
             (void)hipFree(g->block);
         if (g->own_stream)
@@ -555,6 +641,16 @@ int ofl_grid_coef_bias(const ofl_grid *g, float bias[12]) {
             fail(OFL_EINVAL, "NULL argument");
         for (int a = 0; a < kNCoef; ++a)
             bias[a] = g->bias[a];
+    });
+}
+
+int ofl_set_fusion(ofl_grid *g, unsigned flags) {
+    return grid_call(g, [&] {
+        if (flags & ~static_cast<unsigned>(OFL_FUSE_RESIDUAL | OFL_FUSE_COPYBACK_SWAP))
+            fail(OFL_EINVAL, "unknown fusion bits");
+        if (flags != 0 && g->batch_refs > 0)
+            fail(OFL_ESTATE, "a grid inside a batch cannot swap its buffers; destroy the batch first");
+        g->fusion = flags;
     });
 }
 

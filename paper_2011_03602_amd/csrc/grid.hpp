@@ -53,6 +53,13 @@ struct ofl_grid {
     std::vector<int> ev_nest;     // nest of each pair in use
     size_t ev_used = 0;
 
+    // fusion of adjacent GPU nests (gene 111, hoisted): OFL_FUSE_* bits
+    unsigned fusion = 0;
+    double *fused_parts = nullptr;   // one FP64 partial per sweep wave
+    long long fused_parts_cap = 0;
+    bool wrk2_boundary_ok = false;   // device wrk2 carries p's boundary (needed before swapping)
+    unsigned swap_epoch = 0;         // bumped whenever p and wrk2 exchange device buffers
+
     bool broken = false;
     int batch_refs = 0;
 };

@@ -21,6 +21,7 @@
 //    that neighbouring j-blocks run on the same XCD (shared L2);
 //  * no MFMA: there is no dense contraction here.
 
+#include <algorithm>
 #include <array>
 #include <type_traits>
 #include <utility>
@@ -168,20 +169,26 @@ __device__ __forceinline__ void load_coefs(const GridView &g, long long off, flo
 // advances through contiguous memory). Either way rows j-1..j+1 of planes
 // k-1..k+1 stay in registers and each step loads only the three new rows.
 template <int VEC, bool BF16, int FLAGS>
-__device__ __forceinline__ void sweep_march(const GridView &g, int ts, int fixed, int m0, int m1, float omega) {
+__device__ __forceinline__ void sweep_march(const GridView &g, int ts, int fixed, int m0, int m1, float omega,
+                                            double *part) {
+    constexpr bool kFuseR = (FLAGS & kFlagFuseResidual) != 0;
     constexpr bool kNtLoads = (FLAGS & OFL_TILE_NT_LOADS) != 0;
     constexpr bool kNtStores = (FLAGS & OFL_TILE_NT_STORES) != 0;
     constexpr bool kPrefetch = (FLAGS & OFL_TILE_PREFETCH) != 0;
     constexpr bool kMarchJ = (FLAGS & OFL_TILE_MARCH_J) != 0;
     const int lane = threadIdx.x & (kWave - 1);
     const int ib = ts + lane * VEC;
+    // Lanes whose vector starts past the row's last element load the row's
+    // last vector instead (same cache line, no extra HBM traffic); their
+    // results are never stored.
+    const int il = min(ib, ((g.I - 1) / VEC) * VEC);
     const long long pitch = g.pitch;
     const long long plane = g.plane;
     const float *__restrict__ p = g.p;
     auto row = [&](int j, int k) { return p + j * pitch + k * plane; };
     // offset of the coefficients of step m, and of the step after it
     auto coef_off = [&](int m) {
-        return kMarchJ ? m * pitch + fixed * plane + ib : fixed * pitch + m * plane + ib;
+        return kMarchJ ? m * pitch + fixed * plane + il : fixed * pitch + m * plane + il;
     };
 
     // P[r][q][e]: row j-1+r, plane k-1+q, element e. EL/ER: outer neighbours.
@@ -195,9 +202,9 @@ __device__ __forceinline__ void sweep_march(const GridView &g, int ts, int fixed
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
                 if constexpr (kMarchJ)
-                    issue_prow<VEC>(row(m0 - 1 + a, fixed - 1 + b), ib, ts, lane, P[a][b], h[a][b]);
+                    issue_prow<VEC>(row(m0 - 1 + a, fixed - 1 + b), il, ts, lane, P[a][b], h[a][b]);
                 else
-                    issue_prow<VEC>(row(fixed - 1 + b, m0 - 1 + a), ib, ts, lane, P[b][a], h[a][b]);
+                    issue_prow<VEC>(row(fixed - 1 + b, m0 - 1 + a), il, ts, lane, P[b][a], h[a][b]);
             }
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -216,6 +223,7 @@ __device__ __forceinline__ void sweep_march(const GridView &g, int ts, int fixed
 
     const int I = g.I;
     float *__restrict__ wrk2 = g.wrk2;
+    double racc = 0.0;  // fused residual: sum of (wrk2 - p)^2 over this wave's points
     for (int m = m0; m < m1; ++m) {
         const int j = kMarchJ ? m : fixed;
         const int k = kMarchJ ? fixed : m;
@@ -232,9 +240,9 @@ __device__ __forceinline__ void sweep_march(const GridView &g, int ts, int fixed
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
             if constexpr (kMarchJ)
-                issue_prow<VEC>(row(j + 1, k - 1 + b), ib, ts, lane, P[2][b], h[b]);
+                issue_prow<VEC>(row(j + 1, k - 1 + b), il, ts, lane, P[2][b], h[b]);
             else
-                issue_prow<VEC>(row(j - 1 + b, k + 1), ib, ts, lane, P[b][2], h[b]);
+                issue_prow<VEC>(row(j - 1 + b, k + 1), il, ts, lane, P[b][2], h[b]);
         }
         // Keep every load of the step ahead of the first use, so one wait
         // covers them all instead of the scheduler trading them for registers.
@@ -261,6 +269,13 @@ __device__ __forceinline__ void sweep_march(const GridView &g, int ts, int fixed
             s0 += C[7][e] * lf(1, 1) + C[8][e] * P[0][1][e] + C[9][e] * P[1][0][e] + C[11][e];
             const float ss = (C[3][e] * s0 - centre) * C[10][e];
             out[e] = centre + omega * ss;
+            if constexpr (kFuseR) {
+                // the residual nest's own term, (wrk2 - p) in FP32 squared in FP64
+                if (ib + e >= 1 && ib + e <= I - 2) {
+                    const double d = static_cast<double>(out[e] - centre);
+                    racc = fma(d, d, racc);
+                }
+            }
         }
         float *w = wrk2 + j * pitch + k * plane + ib;
         if (ib >= 1 && ib + VEC - 1 <= I - 2) {
@@ -305,6 +320,14 @@ __device__ __forceinline__ void sweep_march(const GridView &g, int ts, int fixed
                     C[n][e] = Cn[n][e];
         }
     }
+    if constexpr (kFuseR) {
+        // butterfly over the wave, fixed order; lane 0 writes the wave's partial
+#pragma unroll
+        for (int d = kWave / 2; d >= 1; d >>= 1)
+            racc += __shfl_xor(racc, d, kWave);
+        if (lane == 0)
+            *part = racc;
+    }
 }
 
 // Lines a wave may own and the extent of its march, per march axis.
@@ -317,8 +340,12 @@ __device__ __forceinline__ void march_extent(const GridView &g, int &fixed_last,
 
 template <int VEC, bool BF16, int FLAGS>
 __global__ __launch_bounds__(512) void sweep_kernel(GridView g, int chunk, int nti, int nfb, float omega,
-                                                    int remap) {
+                                                    int remap, double *parts) {
     const int L = remap ? xcd_remap(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x);
+    // fused residual: one partial per wave of the launch, every slot written
+    double *part = nullptr;
+    if constexpr ((FLAGS & kFlagFuseResidual) != 0)
+        part = parts + static_cast<long long>(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
     const int it = L % nti;
     const int rest = L / nti;
     const int fb = rest % nfb;
@@ -327,11 +354,15 @@ __global__ __launch_bounds__(512) void sweep_kernel(GridView g, int chunk, int n
     const int fixed = 1 + fb * lines + static_cast<int>(threadIdx.x / kWave);
     int fixed_last, march_end;
     march_extent<FLAGS>(g, fixed_last, march_end);
-    if (fixed > fixed_last)
+    if (fixed > fixed_last) {
+        if constexpr ((FLAGS & kFlagFuseResidual) != 0)
+            if ((threadIdx.x & (kWave - 1)) == 0)
+                *part = 0.0;
         return;
+    }
     const int m0 = 1 + mc * chunk;
     const int m1 = min(m0 + chunk, march_end);
-    sweep_march<VEC, BF16, FLAGS>(g, it * kWave * VEC, fixed, m0, m1, omega);
+    sweep_march<VEC, BF16, FLAGS>(g, it * kWave * VEC, fixed, m0, m1, omega, part);
 }
 
 template <int VEC, bool BF16, int FLAGS>
@@ -351,7 +382,7 @@ __global__ __launch_bounds__(512) void batch_sweep_kernel(const GridView *__rest
             continue;
         const int m0 = 1 + item.mchunk * chunk;
         const int m1 = min(m0 + chunk, march_end);
-        sweep_march<VEC, BF16, FLAGS>(g, item.itile * kWave * VEC, fixed, m0, m1, omega);
+        sweep_march<VEC, BF16, FLAGS>(g, item.itile * kWave * VEC, fixed, m0, m1, omega, nullptr);
     }
 }
 
@@ -388,6 +419,8 @@ __device__ __forceinline__ double acc_value(const Acc &a) {
 
 // Row tile rt of a grid -> offset of this lane's first element; false if the
 // tile index is past the end.
+// (ib receives the lane's first i; the returned offset addresses the lane's
+// load, clamped to the row's last vector like the sweep's loads.)
 template <int VEC>
 __device__ __forceinline__ long long row_tile_offset(const GridView &g, int rt, int nti, int lane, int &ib) {
     const int it = rt % nti;
@@ -396,7 +429,8 @@ __device__ __forceinline__ long long row_tile_offset(const GridView &g, int rt, 
     const int j = 1 + row % jj;
     const int k = 1 + row / jj;
     ib = it * kWave * VEC + lane * VEC;
-    return j * static_cast<long long>(g.pitch) + k * g.plane + ib;
+    const int il = min(ib, ((g.I - 1) / VEC) * VEC);
+    return j * static_cast<long long>(g.pitch) + k * g.plane + il;
 }
 
 // Sum of squared differences over row tiles [first, first + count) for one
@@ -499,6 +533,27 @@ __device__ __forceinline__ void finalize_sum(const double *partials, int n, doub
 __global__ __launch_bounds__(kResidualThreads) void finalize_kernel(const double *partials, int n, double omega,
                                                                     double *gosa) {
     finalize_sum(partials, n, omega, gosa);
+}
+
+// First stage of a two-stage fixed-order sum: block b adds partials
+// [b*chunk, (b+1)*chunk) into out[b] (thread strides, then a fixed tree).
+__global__ __launch_bounds__(kResidualThreads) void reduce_stage_kernel(const double *partials, long long n,
+                                                                        long long chunk, double *out) {
+    __shared__ double sm[kResidualThreads];
+    const long long lo = blockIdx.x * chunk;
+    const long long hi = min(n, lo + chunk);
+    double v = 0.0;
+    for (long long t = lo + threadIdx.x; t < hi; t += kResidualThreads)
+        v += partials[t];
+    sm[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = kResidualThreads / 2; h >= 1; h >>= 1) {
+        if (static_cast<int>(threadIdx.x) < h)
+            sm[threadIdx.x] += sm[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        out[blockIdx.x] = sm[0];
 }
 
 __global__ __launch_bounds__(kResidualThreads) void batch_finalize_kernel(const GridView *__restrict__ views,
@@ -633,14 +688,15 @@ void check_launch(const char *what) { hip_check(hipGetLastError(), what); }
 namespace {
 
 // Launcher tables over (vec, format, flags): one instantiation per combination.
-using SweepLaunch = void (*)(const GridView &, const TileCfg &, float, int, int, int, int, hipStream_t);
+using SweepLaunch = void (*)(const GridView &, const TileCfg &, float, int, int, int, double *, hipStream_t);
 using BatchSweepLaunch = void (*)(const GridView *, const SweepItem *, int, const TileCfg &, float, int,
                                   hipStream_t);
 
 template <int VEC, bool BF16, int FLAGS>
-void sweep_one(const GridView &g, const TileCfg &t, float omega, int nti, int nfb, int blocks, int, hipStream_t s) {
+void sweep_one(const GridView &g, const TileCfg &t, float omega, int nti, int nfb, int blocks, double *parts,
+               hipStream_t s) {
     sweep_kernel<VEC, BF16, FLAGS><<<blocks, kWave * t.rows, 0, s>>>(g, t.kchunk, nti, nfb, omega,
-                                                                      (t.flags & OFL_TILE_XCD_REMAP) ? 1 : 0);
+                                                                      (t.flags & OFL_TILE_XCD_REMAP) ? 1 : 0, parts);
 }
 
 template <int VEC, bool BF16, int FLAGS>
@@ -660,16 +716,21 @@ constexpr std::array<BatchSweepLaunch, sizeof...(F)> batch_sweep_row(std::intege
     return {&batch_sweep_one<VEC, BF16, F>...};
 }
 
-constexpr int kFlagCombos = 16;
+constexpr int kFlagCombos = 16;  // template flag bits of the batched sweep
+constexpr int kSweepCombos = 32; // plus the fused-residual bit for the single-grid sweep
 using FlagSeq = std::make_integer_sequence<int, kFlagCombos>;
+using SweepFlagSeq = std::make_integer_sequence<int, kSweepCombos>;
+static_assert((kTemplateFlagMask | kFlagFuseResidual) < kSweepCombos, "sweep launcher table too small");
+static_assert(kTemplateFlagMask < kFlagCombos, "batched sweep launcher table too small");
 
 int vec_index(int vec) { return vec == 1 ? 0 : (vec == 2 ? 1 : 2); }
 
 SweepLaunch sweep_launcher(int vec, bool bf16, int flags) {
-    static const std::array<SweepLaunch, kFlagCombos> table[2][3] = {
-        {sweep_row<1, false>(FlagSeq{}), sweep_row<2, false>(FlagSeq{}), sweep_row<4, false>(FlagSeq{})},
-        {sweep_row<1, true>(FlagSeq{}), sweep_row<2, true>(FlagSeq{}), sweep_row<4, true>(FlagSeq{})}};
-    return table[bf16 ? 1 : 0][vec_index(vec)][flags & (kFlagCombos - 1)];
+    static const std::array<SweepLaunch, kSweepCombos> table[2][3] = {
+        {sweep_row<1, false>(SweepFlagSeq{}), sweep_row<2, false>(SweepFlagSeq{}),
+         sweep_row<4, false>(SweepFlagSeq{})},
+        {sweep_row<1, true>(SweepFlagSeq{}), sweep_row<2, true>(SweepFlagSeq{}), sweep_row<4, true>(SweepFlagSeq{})}};
+    return table[bf16 ? 1 : 0][vec_index(vec)][flags & (kSweepCombos - 1)];
 }
 
 BatchSweepLaunch batch_sweep_launcher(int vec, bool bf16, int flags) {
@@ -690,19 +751,43 @@ void sweep_shape(int I, int J, int K, const TileCfg &t, int *nti, int *nfb, int 
     *nmc = ((march_j ? J : K) - 2 + t.kchunk - 1) / t.kchunk;
 }
 
-void launch_sweep(const GridView &g, const TileCfg &t, int bf16, float omega, hipStream_t s) {
+long long sweep_waves(int I, int J, int K, const TileCfg &t) {
+    int nti, nfb, nmc;
+    sweep_shape(I, J, K, t, &nti, &nfb, &nmc);
+    return static_cast<long long>(nti) * nfb * nmc * t.rows;
+}
+
+void launch_sweep(const GridView &g, const TileCfg &t, int bf16, float omega, hipStream_t s, double *fused_parts) {
     int nti, nfb, nmc;
     sweep_shape(g.I, g.J, g.K, t, &nti, &nfb, &nmc);
     const long long blocks = static_cast<long long>(nti) * nfb * nmc;
     if (blocks > 0x7fffffffLL)
         fail(OFL_EINVAL, "sweep launch too large for this tile");
-    sweep_launcher(t.vec, bf16 != 0, t.flags)(g, t, omega, nti, nfb, static_cast<int>(blocks), 0, s);
+    const int flags = (t.flags & kTemplateFlagMask) | (fused_parts ? kFlagFuseResidual : 0);
+    sweep_launcher(t.vec, bf16 != 0, flags)(g, t, omega, nti, nfb, static_cast<int>(blocks), fused_parts, s);
     check_launch("sweep kernel launch");
+}
+
+void launch_finalize(const double *partials, long long n, float omega, double *gosa, hipStream_t s,
+                     double *scratch, int scratch_len) {
+    constexpr long long kStageChunk = 4 * kResidualThreads;
+    if (n > kStageChunk && scratch && scratch_len > 0) {
+        const long long blocks = std::min<long long>(scratch_len, (n + kStageChunk - 1) / kStageChunk);
+        const long long chunk = (n + blocks - 1) / blocks;
+        reduce_stage_kernel<<<static_cast<int>(blocks), kResidualThreads, 0, s>>>(partials, n, chunk, scratch);
+        check_launch("residual reduce-stage launch");
+        finalize_kernel<<<1, kResidualThreads, 0, s>>>(scratch, static_cast<int>(blocks), static_cast<double>(omega),
+                                                       gosa);
+    } else {
+        finalize_kernel<<<1, kResidualThreads, 0, s>>>(partials, static_cast<int>(n), static_cast<double>(omega), gosa);
+    }
+    check_launch("residual finalize launch");
 }
 
 void launch_batch_sweep(const GridView *views, const SweepItem *items, int nitems, const TileCfg &t, int bf16,
                         float omega, int grid_blocks, hipStream_t s) {
-    batch_sweep_launcher(t.vec, bf16 != 0, t.flags)(views, items, nitems, t, omega, grid_blocks, s);
+    batch_sweep_launcher(t.vec, bf16 != 0, t.flags & kTemplateFlagMask)(views, items, nitems, t, omega, grid_blocks,
+                                                                          s);
     check_launch("batched sweep kernel launch");
 }
 

@@ -21,6 +21,12 @@ constexpr size_t kGuard = 1024;   // elements of slack before and after every de
 constexpr int kResidualBlocks = 2048;  // fixed -> deterministic residual partials
 constexpr int kResidualThreads = 256;
 constexpr int kRowUnroll = 4;
+// Template flags of the sweep kernels are the low four OFL_TILE_* bits (the
+// XCD order is a launch argument, not a template flag) plus this internal bit,
+// which sits where the public tile flags keep OFL_TILE_XCD_REMAP: the sweep
+// also accumulates the residual nest's terms into one FP64 partial per wave.
+constexpr int kTemplateFlagMask = 15;
+constexpr int kFlagFuseResidual = 16;
 
 enum Nest { kS = 0, kR = 1, kC = 2 };
 
@@ -88,7 +94,14 @@ __host__ __device__ inline int itiles(int I, int vec) { return (I - 2) / (kWave 
 void sweep_shape(int I, int J, int K, const TileCfg &t, int *nti, int *nfb, int *nmc);
 
 // Single-grid launches (kernels.hip).
-void launch_sweep(const GridView &g, const TileCfg &t, int bf16, float omega, hipStream_t s);
+// fused_parts != nullptr: fuse the residual, one partial per wave (sweep_waves() of them).
+void launch_sweep(const GridView &g, const TileCfg &t, int bf16, float omega, hipStream_t s,
+                  double *fused_parts = nullptr);
+long long sweep_waves(int I, int J, int K, const TileCfg &t);
+// gosa = sum(partials[0..n)) / omega^2 in a fixed order; with scratch (at
+// least scratch_len doubles) large n is summed in two stages.
+void launch_finalize(const double *partials, long long n, float omega, double *gosa, hipStream_t s,
+                     double *scratch = nullptr, int scratch_len = 0);
 void launch_residual(const GridView &g, int vec, int sum_mode, int flags, float omega, hipStream_t s);
 void launch_copyback(const GridView &g, int vec, int flags, hipStream_t s);
 void launch_pack(const void *staging, void *arr, int I, int J, int K, int pitch, int elem_bytes, hipStream_t s);

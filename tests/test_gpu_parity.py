@@ -303,6 +303,65 @@ def test_device_copy_kernel():
     assert torch.equal(src, dst)
 
 
+# ------------------------------------------------------------------ fusion
+
+
+@pytest.mark.parametrize("fusion", [ofl.OFL_FUSE_RESIDUAL, ofl.OFL_FUSE_COPYBACK_SWAP,
+                                    ofl.OFL_FUSE_RESIDUAL | ofl.OFL_FUSE_COPYBACK_SWAP])
+@pytest.mark.parametrize("iters", [1, 6, 7])
+@pytest.mark.parametrize("fmt", [ofl.OFL_COEF_F32, ofl.OFL_COEF_BF16_OFFSET])
+def test_fused_nests_equal_unfused(fusion, iters, fmt):
+    say("fusion", fusion, "iters", iters, "fmt", fmt)
+    a = synth.make_problem(131, 37, 45, seed=17)
+    ref, r_ref = run_gpu(a, iters, fmt=fmt)
+    g = ofl.Grid(a, coef_format=fmt)
+    ofl.ofl_set_fusion(g.handle, fusion)
+    r = ofl.ofl_jacobi_run(g.handle, iters, OMEGA)
+    assert np.array_equal(g.p, ref.p)          # same per-point arithmetic, exact exchange
+    assert r == pytest.approx(r_ref, rel=1e-12)  # same terms, another summation order
+    s = ofl.ofl_get_stats(g.handle)
+    assert list(s.gpu_nests) == [iters] * 3 and list(s.cpu_nests) == [0] * 3
+    if fmt == ofl.OFL_COEF_F32:
+        check_against_oracle(a, g, r, iters)
+    ref.close()
+    g.close()
+
+
+def test_fused_runs_hand_over_state_to_unfused_runs_and_cpu_nests():
+    say("fusion state handover")
+    a = synth.make_problem(70, 41, 33, seed=19)
+    g = ofl.Grid(a)
+    ofl.ofl_set_fusion(g.handle, ofl.OFL_FUSE_RESIDUAL | ofl.OFL_FUSE_COPYBACK_SWAP)
+    ofl.ofl_data_enter(g.handle)
+    ofl.ofl_jacobi_run(g.handle, 3, OMEGA)        # odd count: p lives in the other buffer
+    ofl.ofl_set_fusion(g.handle, 0)
+    ofl.ofl_jacobi_run(g.handle, 2, OMEGA)        # plain GPU nests continue from there
+    ofl.ofl_data_exit(g.handle)
+    ofl.ofl_set_offload_mask(g.handle, ofl.OFL_NEST_SWEEP, ofl.OFL_XFER_PER_ITER)
+    ofl.ofl_jacobi_run(g.handle, 2, OMEGA)        # mixed gene, per-iteration transfers
+    ofl.ofl_set_fusion(g.handle, ofl.OFL_FUSE_COPYBACK_SWAP)
+    ofl.ofl_set_offload_mask(g.handle, ofl.OFL_MASK_ALL_GPU, ofl.OFL_XFER_HOISTED)
+    r = ofl.ofl_jacobi_run(g.handle, 3, OMEGA)    # p re-uploaded: the boundary copy is redone
+    check_against_oracle(a, g, r, 10)
+    g.close()
+
+
+def test_fusion_rejected_inside_a_batch():
+    say("fusion + batch")
+    probs = _small_batch(2)
+    grids = [ofl.Grid(a) for a in probs]
+    b = ofl.ofl_batch_create([g.handle for g in grids])
+    with pytest.raises(ofl.OflError) as e:
+        ofl.ofl_set_fusion(grids[0].handle, ofl.OFL_FUSE_RESIDUAL)
+    assert e.value.code == ofl.OFL_ESTATE
+    ofl.ofl_batch_destroy(b)
+    ofl.ofl_set_fusion(grids[0].handle, ofl.OFL_FUSE_RESIDUAL)
+    with pytest.raises(ofl.OflError):
+        ofl.ofl_batch_create([g.handle for g in grids])
+    for g in grids:
+        g.close()
+
+
 # ------------------------------------------------------------------- batch
 
 
