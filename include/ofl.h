@@ -284,6 +284,42 @@ typedef struct ofl_tune_result {
 int ofl_grid_tune(ofl_grid *g, const ofl_ga_params *ga, ofl_tune_result *out);
 int ofl_batch_tune(ofl_batch *b, const ofl_ga_params *ga, ofl_tune_result *out);
 
+/* The GA of Sec. 4.2.2 over arbitrary bit genes with a caller-supplied
+ * measurement: the initial population is random (seed_gene joins it), each
+ * distinct gene is measured once by eval(gene, ctx), which returns its time
+ * (> 0), +INFINITY when its result differs from the original program's, or NaN
+ * when the gene cannot be built (both score zero); fitness is 1/sqrt(time);
+ * roulette selection, single-point crossover, per-bit mutation and an
+ * unchanged copy of the elite make each next generation. bits: 1..30. Runs on
+ * the host only (no GPU needed unless eval uses one). EINVAL for bad bits,
+ * parameters or NULL pointers. */
+typedef double (*ofl_gene_eval)(uint32_t gene, void *ctx);
+typedef struct ofl_ga_result {
+    uint32_t best_gene;
+    double best_time;   /* +INFINITY if no gene scored */
+    int evaluated;      /* distinct genes measured */
+    int rejected;       /* genes that were wrong or not buildable */
+} ofl_ga_result;
+int ofl_ga_search(int bits, const ofl_ga_params *ga, uint32_t seed_gene, ofl_gene_eval eval, void *ctx,
+                  ofl_ga_result *out);
+
+/* The paper's loop-offload search (Sec. 3.2.1, Sec. 4.2.2) on one grid: the
+ * gene is the 3-bit offload mask plus one bit for the transfer placement
+ * (bit 3: 1 = hoisted). Each gene runs iters iterations from the grid's current
+ * p with nothing on the device, end to end (transfers included, host clock);
+ * a result that differs from the all-CPU gene's (the original program) beyond
+ * ga->tolerance gets infinite time. The best gene is applied to the grid and
+ * p is restored. Needs a GPU for genes with GPU nests. ESTATE inside a data
+ * region or a batch. */
+typedef struct ofl_offload_result {
+    unsigned mask;      /* best offload gene, bit = 1 -> GPU */
+    int xfer_mode;      /* best placement */
+    double best_ms;     /* its measured time */
+    double cpu_ms;      /* the all-CPU gene's time */
+    int evaluated, rejected;
+} ofl_offload_result;
+int ofl_grid_search_offload(ofl_grid *g, const ofl_ga_params *ga, int iters, float omega, ofl_offload_result *out);
+
 /* ---- measurement helper ---------------------------------------------------- */
 /* Device-to-device copy of bytes (multiple of 16, 16-byte aligned pointers)
  * with the library's streaming copy kernel on the given stream (NULL = the

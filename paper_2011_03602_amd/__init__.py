@@ -82,6 +82,19 @@ class OflTuneResult(ctypes.Structure):
                 ("rejected", ctypes.c_int)]
 
 
+class OflGaResult(ctypes.Structure):
+    _fields_ = [("best_gene", ctypes.c_uint32), ("best_time", ctypes.c_double), ("evaluated", ctypes.c_int),
+                ("rejected", ctypes.c_int)]
+
+
+class OflOffloadResult(ctypes.Structure):
+    _fields_ = [("mask", ctypes.c_uint), ("xfer_mode", ctypes.c_int), ("best_ms", ctypes.c_double),
+                ("cpu_ms", ctypes.c_double), ("evaluated", ctypes.c_int), ("rejected", ctypes.c_int)]
+
+
+OFL_GENE_EVAL = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.c_uint32, ctypes.c_void_p)
+
+
 class OflError(RuntimeError):
     def __init__(self, code: int, message: str):
         super().__init__(f"ofl error {code}: {message}")
@@ -119,6 +132,10 @@ _SIGS = {
     "ofl_batch_run": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "ofl_grid_tune": ([ctypes.c_void_p, ctypes.POINTER(OflGaParams), ctypes.POINTER(OflTuneResult)], ctypes.c_int),
     "ofl_batch_tune": ([ctypes.c_void_p, ctypes.POINTER(OflGaParams), ctypes.POINTER(OflTuneResult)], ctypes.c_int),
+    "ofl_ga_search": ([ctypes.c_int, ctypes.POINTER(OflGaParams), ctypes.c_uint32, OFL_GENE_EVAL, ctypes.c_void_p,
+                       ctypes.POINTER(OflGaResult)], ctypes.c_int),
+    "ofl_grid_search_offload": ([ctypes.c_void_p, ctypes.POINTER(OflGaParams), ctypes.c_int, ctypes.c_float,
+                                 ctypes.POINTER(OflOffloadResult)], ctypes.c_int),
     "ofl_device_copy": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
     "ofl_last_error": ([], ctypes.c_char_p),
     "ofl_version": ([], ctypes.c_char_p),
@@ -290,6 +307,22 @@ def ofl_grid_tune(g, ga: Optional[OflGaParams] = None) -> OflTuneResult:
 def ofl_batch_tune(b, ga: Optional[OflGaParams] = None) -> OflTuneResult:
     r = OflTuneResult()
     _check(lib().ofl_batch_tune(b, ctypes.byref(ga) if ga is not None else None, ctypes.byref(r)))
+    return r
+
+
+def ofl_ga_search(bits: int, evaluate, ga: Optional[OflGaParams] = None, seed_gene: int = 0) -> OflGaResult:
+    """evaluate(gene) -> time (> 0), inf (wrong result) or nan (not buildable)."""
+    cb = OFL_GENE_EVAL(lambda gene, ctx: float(evaluate(int(gene))))
+    r = OflGaResult()
+    _check(lib().ofl_ga_search(bits, ctypes.byref(ga) if ga is not None else None, seed_gene, cb, None,
+                               ctypes.byref(r)))
+    return r
+
+
+def ofl_grid_search_offload(g, iters: int, omega: float, ga: Optional[OflGaParams] = None) -> OflOffloadResult:
+    r = OflOffloadResult()
+    _check(lib().ofl_grid_search_offload(g, ctypes.byref(ga) if ga is not None else None, iters, omega,
+                                         ctypes.byref(r)))
     return r
 
 

@@ -17,6 +17,7 @@
 //   bits 12-13 (batch)  occupancy 0 (one work-group per item), 2, 4, 8 per CU
 //   bit 14 (batch)      vector width chosen per grid (overrides bits 0-1)
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -286,12 +287,18 @@ void check_params(const ofl_ga_params &ga) {
         fail(OFL_EINVAL, "GA parameters out of range");
 }
 
-// The GA proper; evaluate(gene) returns time in ms, +inf for wrong results,
-// or NaN for genes that cannot be built.
+// The GA proper over genes of `bits` bits; evaluate(gene) returns time in
+// ms, +inf for wrong results, or NaN for genes that cannot be built (both
+// score zero). Each distinct gene is evaluated once.
+struct GaOutcome {
+    uint32_t best;
+    double best_t;
+    int evaluated, rejected;
+};
+
 template <class Eval>
-void run_ga(const ofl_ga_params &ga, bool batch, uint32_t seed_gene, Eval &&evaluate, ofl_tune_result *out) {
-    const int bits = gene_bits(batch);
-    const uint32_t full = (1u << bits) - 1u;
+GaOutcome ga_search(const ofl_ga_params &ga, int bits, uint32_t seed_gene, Eval &&evaluate) {
+    const uint32_t full = bits >= 32 ? 0xffffffffu : ((1u << bits) - 1u);
     Rng rng{ga.seed ^ 0x5EEDULL};
     std::vector<uint32_t> pop(static_cast<size_t>(ga.population));
     for (auto &g : pop)
@@ -305,9 +312,11 @@ void run_ga(const ofl_ga_params &ga, bool batch, uint32_t seed_gene, Eval &&eval
         auto it = memo.find(g);
         if (it != memo.end())
             return it->second;
-        const double t = evaluate(g);
-        if (!(t < kInf))
+        double t = evaluate(g);
+        if (!(t > 0.0 && t < kInf)) {  // NaN (not buildable), inf (wrong), or no positive time
             ++rejected;
+            t = kInf;
+        }
         memo[g] = t;
         return t;
     };
@@ -363,13 +372,19 @@ void run_ga(const ofl_ga_params &ga, bool batch, uint32_t seed_gene, Eval &&eval
         }
         pop.swap(next);
     }
+    return GaOutcome{best, best_t, static_cast<int>(memo.size()), rejected};
+}
+
+template <class Eval>
+void run_ga(const ofl_ga_params &ga, bool batch, uint32_t seed_gene, Eval &&evaluate, ofl_tune_result *out) {
+    const GaOutcome r = ga_search(ga, gene_bits(batch), seed_gene, evaluate);
     TileCfg t;
-    if (!(best_t < kInf) || !decode(best, batch, &t))
+    if (!(r.best_t < kInf) || !decode(r.best, batch, &t))
         fail(OFL_ESTATE, "no gene produced a correct result");
     out->best = to_tile(t);
-    out->best_ms = best_t;
-    out->evaluated = static_cast<int>(memo.size());
-    out->rejected = rejected;
+    out->best_ms = r.best_t;
+    out->evaluated = r.evaluated;
+    out->rejected = r.rejected;
 }
 
 ofl_ga_params defaults_or(const ofl_ga_params *ga) {
@@ -395,6 +410,105 @@ ofl_ga_params defaults_or(const ofl_ga_params *ga) {
 using namespace ofl;
 
 extern "C" {
+
+int ofl_ga_search(int bits, const ofl_ga_params *ga_in, uint32_t seed_gene, ofl_gene_eval eval, void *ctx,
+                  ofl_ga_result *out) {
+    return guarded(nullptr, [&] {
+        if (bits < 1 || bits > 30 || !eval || !out)
+            fail(OFL_EINVAL, "bits must be in 1..30 and eval/out must not be NULL");
+        const ofl_ga_params ga = defaults_or(ga_in);
+        check_params(ga);
+        const GaOutcome r = ga_search(ga, bits, seed_gene, [&](uint32_t g) { return eval(g, ctx); });
+        out->best_gene = r.best;
+        out->best_time = r.best_t;
+        out->evaluated = r.evaluated;
+        out->rejected = r.rejected;
+    });
+}
+
+int ofl_grid_search_offload(ofl_grid *g, const ofl_ga_params *ga_in, int iters, float omega,
+                            ofl_offload_result *out) {
+    return guarded(nullptr, [&] {
+        if (!g || !out)
+            fail(OFL_EINVAL, "NULL argument");
+        if (g->broken)
+            fail(OFL_EDEVICE, "grid handle unusable after an earlier device error");
+        if (iters < 1 || !std::isfinite(omega) || omega == 0.f)
+            fail(OFL_EINVAL, "iters must be >= 1 and omega finite and non-zero");
+        if (g->in_region || g->batch_refs > 0)
+            fail(OFL_ESTATE, "close the data region and leave any batch before searching offload genes");
+        const ofl_ga_params ga = defaults_or(ga_in);
+        check_params(ga);
+        // Bring p home, keep the initial iterate; every measurement starts from it
+        // with nothing on the device, so it includes the transfers its gene needs.
+        {
+            std::vector<Xfer> xs;
+            plan_sync_host(-1, g->valid, xs);
+            grid_exec(g, xs);
+            grid_sync(g);
+        }
+        const std::vector<float> p0(g->p, g->p + g->n);
+        const unsigned mask0 = g->mask;
+        const int mode0 = g->mode;
+        auto restore = [&] {
+            grid_sync(g);
+            std::memcpy(g->p, p0.data(), p0.size() * sizeof(float));
+            g->valid = fresh_validity();
+        };
+        auto timed_run = [&](unsigned mask, int mode, double *gosa) {
+            restore();
+            g->mask = mask;
+            g->mode = mode;
+            const auto t0 = std::chrono::steady_clock::now();
+            grid_run_loop(g, iters, omega, 3);
+            std::vector<Xfer> xs;
+            plan_sync_host(iters, g->valid, xs);
+            grid_exec(g, xs);
+            *gosa = grid_fetch_gosa(g);
+            const auto t1 = std::chrono::steady_clock::now();
+            return std::chrono::duration<double, std::milli>(t1 - t0).count();
+        };
+        // The original program: every nest on the CPU. Its result is the reference.
+        double gosa_ref = 0.0;
+        const double cpu_ms = timed_run(OFL_MASK_ALL_CPU, OFL_XFER_HOISTED, &gosa_ref);
+        const std::vector<float> p_ref(g->p, g->p + g->n);
+        double pmax = 0.0;
+        for (float v : p_ref)
+            pmax = std::max(pmax, static_cast<double>(std::fabs(v)));
+        auto evaluate = [&](uint32_t gene) -> double {
+            const unsigned mask = gene & 7u;
+            const int mode = (gene >> 3) & 1u ? OFL_XFER_HOISTED : OFL_XFER_PER_ITER;
+            double gosa = 0.0;
+            const double ms = timed_run(mask, mode, &gosa);
+            double dmax = 0.0;
+            for (size_t t = 0; t < g->n; ++t)
+                dmax = std::max(dmax, std::fabs(static_cast<double>(g->p[t]) - p_ref[t]));
+            const bool ok = dmax <= ga.tolerance * std::max(pmax, 1e-300) &&
+                            std::fabs(gosa - gosa_ref) <= 10.0 * ga.tolerance * std::fabs(gosa_ref);
+            return ok ? ms : kInf;
+        };
+        GaOutcome r;
+        try {
+            r = ga_search(ga, 4, OFL_MASK_ALL_GPU | 8u, evaluate);
+        } catch (...) {
+            restore();
+            g->mask = mask0;
+            g->mode = mode0;
+            throw;
+        }
+        restore();
+        if (!(r.best_t < kInf))
+            fail(OFL_ESTATE, "no offload gene reproduced the all-CPU result");
+        g->mask = r.best & 7u;
+        g->mode = (r.best >> 3) & 1u ? OFL_XFER_HOISTED : OFL_XFER_PER_ITER;
+        out->mask = g->mask;
+        out->xfer_mode = g->mode;
+        out->best_ms = r.best_t;
+        out->cpu_ms = cpu_ms;
+        out->evaluated = r.evaluated;
+        out->rejected = r.rejected;
+    });
+}
 
 int ofl_grid_tune(ofl_grid *g, const ofl_ga_params *ga_in, ofl_tune_result *out) {
     return guarded(nullptr, [&] {

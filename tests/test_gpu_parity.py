@@ -447,6 +447,19 @@ def test_grid_tuner_small_search():
     g.close()
 
 
+def test_offload_gene_search():
+    say("offload gene GA")
+    a = synth.make_problem(66, 35, 40, seed=23)
+    g = ofl.Grid(a)
+    r = ofl.ofl_grid_search_offload(g.handle, 4, OMEGA, ofl.ga_params(population=6, generations=3, seed=9))
+    assert 0 <= r.mask <= 7 and r.xfer_mode in (0, 1)
+    assert r.best_ms > 0 and r.cpu_ms > 0 and r.evaluated >= 2
+    assert np.array_equal(g.p, a["p"])             # the search leaves the iterate alone
+    gosa = ofl.ofl_jacobi_run(g.handle, 4, OMEGA)   # the chosen gene is applied
+    check_against_oracle(a, g, gosa, 4)
+    g.close()
+
+
 def test_batch_tuner_small_search():
     say("batch GA tuner")
     probs = _small_batch(3)
