@@ -110,13 +110,12 @@ def run_single(ofl, arrays, fmt, steps, warmup, tile=None, profile=True, iters=I
     return res
 
 
-def run_batch(ofl, n_grids, fmt, steps, warmup, tune, iters=ITERS):
+def run_batch(ofl, probs, fmt, steps, warmup, tune, iters=ITERS):
+    """The uneven grids in one batch: plain and fused graph runs against the
+    same grids run one after another with single-grid calls."""
     import torch
 
-    import synth
-
-    log(f"generating {n_grids} uneven grids")
-    probs = synth.make_batch(n_grids)
+    n_grids = len(probs)
     total_lups = sum(interior(*shape) for shape, _ in probs) * iters
     grids = [ofl.Grid(arr, coef_format=fmt) for _, arr in probs]
     for g in grids:
@@ -127,14 +126,20 @@ def run_batch(ofl, n_grids, fmt, steps, warmup, tune, iters=ITERS):
         log("GA tile search for the batch")
         r = ofl.ofl_batch_tune(b, ofl.ga_params(population=10, generations=6, probe_iters=10, repeats=2))
         tuned = {"tile": r.best.as_dict(), "probe_ms": r.best_ms, "evaluated": r.evaluated, "rejected": r.rejected}
-    for _ in range(warmup):
-        ofl.ofl_batch_run(b, iters, OMEGA, n_grids)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        ofl.ofl_batch_run(b, iters, OMEGA, n_grids)
-    torch.cuda.synchronize()
-    dt_batch = (time.perf_counter() - t0) / steps
+
+    def timed(fusion):
+        ofl.ofl_batch_set_fusion(b, fusion)
+        for _ in range(warmup):
+            ofl.ofl_batch_run(b, iters, OMEGA, n_grids)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ofl.ofl_batch_run(b, iters, OMEGA, n_grids)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    dt_batch = timed(0)
+    dt_fused = timed(ofl.OFL_FUSE_RESIDUAL | ofl.OFL_FUSE_COPYBACK_SWAP)
     tile_used = ofl.ofl_batch_get_tile(b).as_dict()
     ofl.ofl_batch_destroy(b)
     # baseline: the same grids one after another, plain single-grid runs
@@ -152,10 +157,12 @@ def run_batch(ofl, n_grids, fmt, steps, warmup, tune, iters=ITERS):
     return {
         "grids": n_grids,
         "lattice_updates": total_lups,
-        "glups_batched": total_lups / dt_batch / 1e9,
-        "glups_sequential": total_lups / dt_seq / 1e9,
-        "ms_batched": 1e3 * dt_batch,
-        "ms_sequential": 1e3 * dt_seq,
+        "glups_batched": round(total_lups / dt_batch / 1e9, 3),
+        "glups_batched_fused": round(total_lups / dt_fused / 1e9, 3),
+        "glups_sequential": round(total_lups / dt_seq / 1e9, 3),
+        "ms_batched": round(1e3 * dt_batch, 3),
+        "ms_batched_fused": round(1e3 * dt_fused, 3),
+        "ms_sequential": round(1e3 * dt_seq, 3),
         "tile": tile_used,
         "tuner": tuned,
     }
@@ -315,7 +322,8 @@ def main():
         elif args.profile_only == "bf16":
             run_single(ofl, arrays, ofl.OFL_COEF_BF16_OFFSET, args.steps, args.warmup, profile=False, iters=it)
         elif args.profile_only == "batch":
-            run_batch(ofl, args.batch_grids, ofl.OFL_COEF_F32, args.steps, args.warmup, False, iters=it)
+            run_batch(ofl, synth.make_batch(args.batch_grids), ofl.OFL_COEF_F32, args.steps, args.warmup, False,
+                      iters=it)
         else:
             raise SystemExit(f"unknown --profile-only {args.profile_only}")
         log("profile run done")
@@ -390,13 +398,12 @@ def main():
                 "speedup_vs_f32": round(fr["glups"] / head["glups"], 3),
             }
         if not args.skip_batch:
-            log("batched variant, FP32")
-            bt = run_batch(ofl, args.batch_grids, ofl.OFL_COEF_F32, max(1, args.steps // 2), 1, args.tune_batch)
-            out["variants"]["batched_f32"] = bt
-            log("batched variant, bfloat16-offset")
-            bb = run_batch(ofl, args.batch_grids, ofl.OFL_COEF_BF16_OFFSET, max(1, args.steps // 2), 1,
-                           args.tune_batch)
-            out["variants"]["batched_bf16_offset"] = bb
+            log(f"generating {args.batch_grids} uneven grids")
+            probs = synth.make_batch(args.batch_grids)
+            for name, fmt in (("batched_f32", ofl.OFL_COEF_F32), ("batched_bf16_offset", ofl.OFL_COEF_BF16_OFFSET)):
+                log(f"{name} variant")
+                out["variants"][name] = run_batch(ofl, probs, fmt, max(1, args.steps // 2), 1, args.tune_batch)
+            del probs
     if not args.skip_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(arrays, args.oracle_iters)
     print(json.dumps(out), flush=True)

@@ -247,6 +247,13 @@ void ofl_batch_destroy(ofl_batch *b);
 int ofl_batch_set_tile(ofl_batch *b, const ofl_tile *tile);
 int ofl_batch_get_tile(const ofl_batch *b, ofl_tile *tile);
 
+/* Fusion for the batched iterations (OFL_FUSE_* as for ofl_set_fusion): the
+ * batched sweep also emits each grid's residual partials, and/or the copy-back
+ * becomes an exchange of every grid's p and wrk2 buffers (odd iterations read
+ * a second view table with the two exchanged; after a run of odd length the
+ * grids keep the exchange). EINVAL for unknown bits. */
+int ofl_batch_set_fusion(ofl_batch *b, unsigned flags);
+
 /* iters x (S, R, C) on the GPU for every grid of the batch, inside the
  * grids' data regions when open (else the grids' p are copied back at the
  * end). gosa_out (nullable) receives n residuals, one per grid. The first

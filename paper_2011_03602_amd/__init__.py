@@ -129,6 +129,7 @@ _SIGS = {
     "ofl_batch_destroy": ([ctypes.c_void_p], None),
     "ofl_batch_set_tile": ([ctypes.c_void_p, ctypes.POINTER(OflTile)], ctypes.c_int),
     "ofl_batch_get_tile": ([ctypes.c_void_p, ctypes.POINTER(OflTile)], ctypes.c_int),
+    "ofl_batch_set_fusion": ([ctypes.c_void_p, ctypes.c_uint], ctypes.c_int),
     "ofl_batch_run": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "ofl_grid_tune": ([ctypes.c_void_p, ctypes.POINTER(OflGaParams), ctypes.POINTER(OflTuneResult)], ctypes.c_int),
     "ofl_batch_tune": ([ctypes.c_void_p, ctypes.POINTER(OflGaParams), ctypes.POINTER(OflTuneResult)], ctypes.c_int),
@@ -285,6 +286,10 @@ def ofl_batch_get_tile(b) -> OflTile:
     t = OflTile()
     _check(lib().ofl_batch_get_tile(b, ctypes.byref(t)))
     return t
+
+
+def ofl_batch_set_fusion(b, flags: int) -> None:
+    _check(lib().ofl_batch_set_fusion(b, flags))
 
 
 def ofl_batch_run(b, iters: int, omega: float, n_grids: int):

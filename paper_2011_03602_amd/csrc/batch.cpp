@@ -42,6 +42,9 @@ void drop_graph(ofl_batch *b) {
 void free_tables(ofl_batch *b) {
     drop_graph(b);
     free_dev(b->d_views);
+    free_dev(b->d_views_swapped);
+    free_dev(b->d_fparts);
+    free_dev(b->d_frange);
     free_dev(b->d_sitems);
     free_dev(b->d_ritems);
     free_dev(b->d_range);
@@ -60,6 +63,31 @@ void upload(void *&dst, const std::vector<T> &src, hipStream_t s) {
 }
 
 }  // namespace
+
+// Device view tables from the grids' current views: as held (even iterations)
+// and with p and wrk2 exchanged (odd iterations of a swapping run).
+void batch_upload_views(ofl_batch *b) {
+    const size_t n = b->grids.size();
+    std::vector<GridView> views(n), swapped(n);
+    for (size_t g = 0; g < n; ++g) {
+        views[g] = b->grids[g]->view;
+        views[g].partials = static_cast<double *>(b->d_partials) + b->partial_base[g];
+        swapped[g] = views[g];
+        std::swap(swapped[g].p, swapped[g].wrk2);
+    }
+    if (b->d_views && b->d_views_swapped) {
+        // in place: a captured graph keeps reading these two buffers
+        hip_check(hipMemcpyAsync(b->d_views, views.data(), n * sizeof(GridView), hipMemcpyHostToDevice, b->stream),
+                  "hipMemcpyAsync(batch views)");
+        hip_check(hipMemcpyAsync(b->d_views_swapped, swapped.data(), n * sizeof(GridView), hipMemcpyHostToDevice,
+                                 b->stream),
+                  "hipMemcpyAsync(batch views)");
+    } else {
+        upload(b->d_views, views, b->stream);
+        upload(b->d_views_swapped, swapped, b->stream);
+    }
+    hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize(batch views)");
+}
 
 // Vector width for a grid of I points along i: the one whose wave tiles cover
 // the interior with the fewest idle lanes; wider wins ties within 5%.
@@ -136,12 +164,21 @@ void batch_build_tables(ofl_batch *b) {
     const hipStream_t s = b->stream;
     hip_check(hipMalloc(&b->d_partials, sizeof(double) * std::max(1, range[static_cast<size_t>(n)])),
               "hipMalloc(batch partials)");
-    std::vector<GridView> views(static_cast<size_t>(n));
-    for (int g = 0; g < n; ++g) {
-        views[static_cast<size_t>(g)] = b->grids[static_cast<size_t>(g)]->view;
-        views[static_cast<size_t>(g)].partials = static_cast<double *>(b->d_partials) + range[static_cast<size_t>(g)];
-    }
-    upload(b->d_views, views, s);
+    b->partial_base.assign(static_cast<size_t>(n), 0);
+    for (int g = 0; g < n; ++g)
+        b->partial_base[static_cast<size_t>(g)] = range[static_cast<size_t>(g)];
+    batch_upload_views(b);
+    // fused residual: grid g owns the partial slots of its sweep items (rows
+    // slots per item), which are contiguous in the concatenated list; the
+    // table holds [first slot, end slot) for every grid.
+    std::vector<long long> frange(2 * static_cast<size_t>(n), 0);
+    for (size_t w = sitems.size(); w-- > 0;)
+        frange[2 * static_cast<size_t>(sitems[w].grid)] = static_cast<long long>(w) * b->tile.rows;
+    for (size_t w = 0; w < sitems.size(); ++w)
+        frange[2 * static_cast<size_t>(sitems[w].grid) + 1] = static_cast<long long>(w + 1) * b->tile.rows;
+    hip_check(hipMalloc(&b->d_fparts, sizeof(double) * std::max<size_t>(1, sitems.size() * b->tile.rows)),
+              "hipMalloc(batch fused partials)");
+    upload(b->d_frange, frange, s);
     upload(b->d_sitems, sitems, s);
     upload(b->d_ritems, ritems, s);
     upload(b->d_range, range, s);
@@ -173,32 +210,47 @@ int blocks_for(const ofl_batch *b, int nitems) {
 }  // namespace
 
 // Enqueue iters x (S, R, finalize, C) for every grid on the batch stream:
-// per nest one batched launch per vector-width class that has work.
+// per nest one batched launch per vector-width class that has work. With
+// OFL_FUSE_RESIDUAL the sweep emits the residual partials (then one finalize
+// per grid); with OFL_FUSE_COPYBACK_SWAP there is no copy-back and odd
+// iterations read the view table with p and wrk2 exchanged.
 void batch_enqueue(ofl_batch *b, int iters, float omega) {
-    const auto *views = static_cast<const GridView *>(b->d_views);
+    const auto *views_even = static_cast<const GridView *>(b->d_views);
+    const auto *views_odd = static_cast<const GridView *>(b->d_views_swapped);
     const auto *sitems = static_cast<const SweepItem *>(b->d_sitems);
     const auto *ritems = static_cast<const RowItem *>(b->d_ritems);
     const auto *range = static_cast<const int *>(b->d_range);
+    auto *fparts = static_cast<double *>(b->d_fparts);
+    const auto *frange = static_cast<const long long *>(b->d_frange);
+    const bool fuse_r = (b->fusion & OFL_FUSE_RESIDUAL) != 0;
+    const bool swap = (b->fusion & OFL_FUSE_COPYBACK_SWAP) != 0;
     const int n = static_cast<int>(b->grids.size());
     const int vecs[3] = {1, 2, 4};
     for (int it = 0; it < iters; ++it) {
+        const GridView *views = (swap && (it & 1)) ? views_odd : views_even;
         for (int c = 0; c < 3; ++c) {
             if (b->s_cnt[c] == 0)
                 continue;
             TileCfg t = b->tile;
             t.vec = vecs[c];
             launch_batch_sweep(views, sitems + b->s_off[c], b->s_cnt[c], t, b->fmt != OFL_COEF_F32, omega,
-                               blocks_for(b, b->s_cnt[c]), b->stream);
+                               blocks_for(b, b->s_cnt[c]), b->stream,
+                               fuse_r ? fparts + static_cast<long long>(b->s_off[c]) * b->tile.rows : nullptr);
         }
-        for (int c = 0; c < 3; ++c)
-            if (b->r_cnt[c] > 0)
-                launch_batch_residual(views, ritems + b->r_off[c], b->r_cnt[c], vecs[c], b->sum_mode, b->tile.flags,
-                                      blocks_for(b, b->r_cnt[c]), b->stream);
-        launch_batch_finalize(views, range, n, omega, b->stream);
-        for (int c = 0; c < 3; ++c)
-            if (b->r_cnt[c] > 0)
-                launch_batch_copyback(views, ritems + b->r_off[c], b->r_cnt[c], vecs[c], b->tile.flags,
-                                      blocks_for(b, b->r_cnt[c]), b->stream);
+        if (fuse_r) {
+            launch_batch_finalize_parts(views, fparts, frange, n, omega, b->stream);
+        } else {
+            for (int c = 0; c < 3; ++c)
+                if (b->r_cnt[c] > 0)
+                    launch_batch_residual(views, ritems + b->r_off[c], b->r_cnt[c], vecs[c], b->sum_mode,
+                                          b->tile.flags, blocks_for(b, b->r_cnt[c]), b->stream);
+            launch_batch_finalize(views, range, n, omega, b->stream);
+        }
+        if (!swap)
+            for (int c = 0; c < 3; ++c)
+                if (b->r_cnt[c] > 0)
+                    launch_batch_copyback(views, ritems + b->r_off[c], b->r_cnt[c], vecs[c], b->tile.flags,
+                                          blocks_for(b, b->r_cnt[c]), b->stream);
     }
 }
 
@@ -209,13 +261,15 @@ void batch_prepare(ofl_batch *b) {
         std::vector<Xfer> xs;
         plan_enter(OFL_MASK_ALL_GPU, g->valid, xs);
         grid_exec(g, xs);
+        if (b->fusion & OFL_FUSE_COPYBACK_SWAP)
+            grid_sync_wrk2_boundary(g);
         grid_sync(g);
     }
     batch_build_tables(b);
 }
 
 void batch_launch(ofl_batch *b, int iters, float omega) {
-    const bool reuse = b->exec && b->graph_iters == iters && b->graph_omega == omega;
+    const bool reuse = b->exec && b->graph_iters == iters && b->graph_omega == omega && b->graph_fusion == b->fusion;
     if (!reuse) {
         drop_graph(b);
         hipGraph_t graph = nullptr;
@@ -234,6 +288,7 @@ void batch_launch(ofl_batch *b, int iters, float omega) {
         hip_check(e, "hipGraphInstantiate");
         b->graph_iters = iters;
         b->graph_omega = omega;
+        b->graph_fusion = b->fusion;
     }
     hip_check(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch");
 }
@@ -251,8 +306,19 @@ void batch_mark_done(ofl_batch *b, int iters) {
     }
 }
 
+// After a swapping run of odd length every grid's p lives in its former
+// wrk2 buffer: record the exchange and refresh both view tables in place.
+void batch_after_run(ofl_batch *b, int iters) {
+    if ((b->fusion & OFL_FUSE_COPYBACK_SWAP) && (iters & 1)) {
+        for (ofl_grid *g : b->grids)
+            grid_swap_p_wrk2(g);
+        batch_upload_views(b);
+    }
+}
+
 void batch_finish(ofl_batch *b, int iters, double *gosa_out) {
     hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize(batch)");
+    batch_after_run(b, iters);
     batch_mark_done(b, iters);
     for (size_t t = 0; t < b->grids.size(); ++t) {
         ofl_grid *g = b->grids[t];
@@ -359,6 +425,21 @@ int ofl_batch_set_tile(ofl_batch *b, const ofl_tile *tile) {
             hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
             free_tables(b);
             b->tile = c;
+        }
+    });
+}
+
+int ofl_batch_set_fusion(ofl_batch *b, unsigned flags) {
+    return guarded(nullptr, [&] {
+        if (!b)
+            fail(OFL_EINVAL, "NULL batch handle");
+        if (flags & ~static_cast<unsigned>(OFL_FUSE_RESIDUAL | OFL_FUSE_COPYBACK_SWAP))
+            fail(OFL_EINVAL, "unknown fusion bits");
+        if (flags != b->fusion) {
+            hip_check(hipSetDevice(b->device), "hipSetDevice");
+            hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+            drop_graph(b);
+            b->fusion = flags;
         }
     });
 }

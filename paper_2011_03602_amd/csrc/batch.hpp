@@ -15,8 +15,13 @@ struct ofl_batch {
     hipStream_t stream = nullptr;
     ofl::TileCfg tile;
 
+    unsigned fusion = 0;  // OFL_FUSE_* bits for the batched iterations
+
     bool tables_ready = false;
-    void *d_views = nullptr;
+    void *d_views = nullptr;          // views as the grids hold them (even iterations)
+    void *d_views_swapped = nullptr;  // p and wrk2 exchanged (odd iterations of a swapping run)
+    void *d_fparts = nullptr;         // fused residual: one partial per sweep wave
+    void *d_frange = nullptr;         // per grid, its range of d_fparts (ngrids + 1 entries)
     void *d_sitems = nullptr;
     void *d_ritems = nullptr;
     void *d_range = nullptr;
@@ -24,9 +29,12 @@ struct ofl_batch {
     int s_off[3] = {}, s_cnt[3] = {};  // sweep items per vector-width class (1, 2, 4)
     int r_off[3] = {}, r_cnt[3] = {};  // residual/copy-back items per class
 
+    std::vector<int> partial_base;  // per grid, its first residual partial
+
     hipGraphExec_t exec = nullptr;
     int graph_iters = -1;
     float graph_omega = NAN;
+    unsigned graph_fusion = 0;
 };
 
 namespace ofl {
@@ -37,6 +45,8 @@ void batch_enqueue(ofl_batch *b, int iters, float omega);
 void batch_launch(ofl_batch *b, int iters, float omega);
 void batch_finish(ofl_batch *b, int iters, double *gosa_out);
 void batch_mark_done(ofl_batch *b, int iters);
+void batch_after_run(ofl_batch *b, int iters);
+void batch_upload_views(ofl_batch *b);
 int batch_auto_vec(int I);
 bool batch_auto_vec_tile(const ofl_tile &t);
 

@@ -270,12 +270,6 @@ void cpu_nest(ofl_grid *g, int nest, float omega) {
 
 namespace {
 
-// p and wrk2 exchange device buffers: the copy-back of a fused iteration.
-void swap_p_wrk2(ofl_grid *g) {
-    std::swap(g->lay.off[OFL_ARR_P], g->lay.off[OFL_ARR_WRK2]);
-    std::swap(g->view.p, g->view.wrk2);
-    g->swap_epoch += 1;
-}
 
 // Fused iterations (gene 111, hoisted, fusion requested): the sweep also
 // produces the residual's per-wave partials (OFL_FUSE_RESIDUAL), and the
@@ -305,12 +299,8 @@ void run_fused(ofl_grid *g, int iters, float omega) {
         xs.clear();
         plan_before(it, kS, true, OFL_XFER_HOISTED, g->valid, xs);
         grid_exec(g, xs);
-        if (swap && !g->wrk2_boundary_ok) {
-            // whole-array copy p -> wrk2 once, so both buffers share the boundary
-            const size_t bytes = g->lay.elems * sizeof(float);
-            launch_copy(grid_array_ptr(g, OFL_ARR_WRK2), grid_array_ptr(g, OFL_ARR_P), bytes, g->stream);
-            g->wrk2_boundary_ok = true;
-        }
+        if (swap)
+            grid_sync_wrk2_boundary(g);
         prof_begin(g, kS);
         launch_sweep(g->view, g->tile, g->fmt != OFL_COEF_F32, omega, g->stream, fuse_r ? g->fused_parts : nullptr);
         prof_end(g);
@@ -330,7 +320,7 @@ void run_fused(ofl_grid *g, int iters, float omega) {
         g->gosa_on_dev = true;
         g->stats.gpu_nests[kR] += 1;
         if (swap) {
-            swap_p_wrk2(g);
+            grid_swap_p_wrk2(g);
         } else {
             prof_begin(g, kC);
             launch_copyback(g->view, g->tile.vec, g->tile.flags, g->stream);
@@ -434,6 +424,22 @@ int grid_call(ofl_grid *g, F &&f) {
 }
 
 }  // namespace
+
+// p and wrk2 exchange device buffers: the copy-back of a fused iteration.
+void grid_swap_p_wrk2(ofl_grid *g) {
+    std::swap(g->lay.off[OFL_ARR_P], g->lay.off[OFL_ARR_WRK2]);
+    std::swap(g->view.p, g->view.wrk2);
+    g->swap_epoch += 1;
+}
+
+// Give the device wrk2 p's boundary (both buffers then share it), once per upload of p.
+void grid_sync_wrk2_boundary(ofl_grid *g) {
+    if (g->wrk2_boundary_ok)
+        return;
+    launch_copy(grid_array_ptr(g, OFL_ARR_WRK2), grid_array_ptr(g, OFL_ARR_P), g->lay.elems * sizeof(float), g->stream);
+    g->wrk2_boundary_ok = true;
+    g->pending = true;
+}
 
 void grid_sync(ofl_grid *g) {
     if (!g->dev_ready)

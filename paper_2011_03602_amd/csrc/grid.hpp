@@ -73,5 +73,7 @@ void grid_exec(ofl_grid *g, const std::vector<Xfer> &xs);
 void *grid_array_ptr(ofl_grid *g, int a);
 void grid_run_loop(ofl_grid *g, int iters, float omega, int nests);
 double grid_fetch_gosa(ofl_grid *g);
+void grid_swap_p_wrk2(ofl_grid *g);
+void grid_sync_wrk2_boundary(ofl_grid *g);
 
 }  // namespace ofl

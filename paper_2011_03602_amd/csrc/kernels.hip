@@ -365,24 +365,34 @@ __global__ __launch_bounds__(512) void sweep_kernel(GridView g, int chunk, int n
     sweep_march<VEC, BF16, FLAGS>(g, it * kWave * VEC, fixed, m0, m1, omega, part);
 }
 
+// parts (fused residual only): slot w*lines + wave receives the partial of
+// wave `wave` of item w; every slot of every item is written.
 template <int VEC, bool BF16, int FLAGS>
 __global__ __launch_bounds__(512) void batch_sweep_kernel(const GridView *__restrict__ views,
                                                           const SweepItem *__restrict__ items, int nitems,
-                                                          int chunk, float omega, int remap) {
+                                                          int chunk, float omega, int remap, double *parts) {
+    constexpr bool kFuseR = (FLAGS & kFlagFuseResidual) != 0;
     const int lines = blockDim.x / kWave;
     const int wave = static_cast<int>(threadIdx.x / kWave);
     const int first = remap ? xcd_remap(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x);
     for (int w = first; w < nitems; w += gridDim.x) {
         const SweepItem item = items[w];
         const GridView g = views[item.grid];
+        double *part = nullptr;
+        if constexpr (kFuseR)
+            part = parts + static_cast<long long>(w) * lines + wave;
         const int fixed = 1 + item.fblock * lines + wave;
         int fixed_last, march_end;
         march_extent<FLAGS>(g, fixed_last, march_end);
-        if (fixed > fixed_last)
+        if (fixed > fixed_last) {
+            if constexpr (kFuseR)
+                if ((threadIdx.x & (kWave - 1)) == 0)
+                    *part = 0.0;
             continue;
+        }
         const int m0 = 1 + item.mchunk * chunk;
         const int m1 = min(m0 + chunk, march_end);
-        sweep_march<VEC, BF16, FLAGS>(g, item.itile * kWave * VEC, fixed, m0, m1, omega, nullptr);
+        sweep_march<VEC, BF16, FLAGS>(g, item.itile * kWave * VEC, fixed, m0, m1, omega, part);
     }
 }
 
@@ -564,6 +574,28 @@ __global__ __launch_bounds__(kResidualThreads) void batch_finalize_kernel(const 
     finalize_sum(g.partials, range[blockIdx.x + 1] - range[blockIdx.x], omega, g.gosa);
 }
 
+// Fused batches: grid b sums parts[range[2b] .. range[2b+1]) (its sweep waves).
+__global__ __launch_bounds__(kResidualThreads) void batch_finalize_parts_kernel(const GridView *__restrict__ views,
+                                                                                const double *__restrict__ parts,
+                                                                                const long long *__restrict__ range,
+                                                                                double omega) {
+    __shared__ double sm[kResidualThreads];
+    const long long lo = range[2 * blockIdx.x];
+    const long long hi = range[2 * blockIdx.x + 1];
+    double v = 0.0;
+    for (long long t = lo + threadIdx.x; t < hi; t += kResidualThreads)
+        v += parts[t];
+    sm[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = kResidualThreads / 2; h >= 1; h >>= 1) {
+        if (static_cast<int>(threadIdx.x) < h)
+            sm[threadIdx.x] += sm[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        *views[blockIdx.x].gosa = sm[0] / (omega * omega);
+}
+
 // ---------------------------------------------------------------- copy-back
 
 template <int VEC, bool NTL, bool NTS>
@@ -689,7 +721,7 @@ namespace {
 
 // Launcher tables over (vec, format, flags): one instantiation per combination.
 using SweepLaunch = void (*)(const GridView &, const TileCfg &, float, int, int, int, double *, hipStream_t);
-using BatchSweepLaunch = void (*)(const GridView *, const SweepItem *, int, const TileCfg &, float, int,
+using BatchSweepLaunch = void (*)(const GridView *, const SweepItem *, int, const TileCfg &, float, int, double *,
                                   hipStream_t);
 
 template <int VEC, bool BF16, int FLAGS>
@@ -701,9 +733,9 @@ void sweep_one(const GridView &g, const TileCfg &t, float omega, int nti, int nf
 
 template <int VEC, bool BF16, int FLAGS>
 void batch_sweep_one(const GridView *views, const SweepItem *items, int nitems, const TileCfg &t, float omega,
-                     int blocks, hipStream_t s) {
-    batch_sweep_kernel<VEC, BF16, FLAGS><<<blocks, kWave * t.rows, 0, s>>>(views, items, nitems, t.kchunk, omega,
-                                                                            (t.flags & OFL_TILE_XCD_REMAP) ? 1 : 0);
+                     int blocks, double *parts, hipStream_t s) {
+    batch_sweep_kernel<VEC, BF16, FLAGS><<<blocks, kWave * t.rows, 0, s>>>(
+        views, items, nitems, t.kchunk, omega, (t.flags & OFL_TILE_XCD_REMAP) ? 1 : 0, parts);
 }
 
 template <int VEC, bool BF16, int... F>
@@ -716,12 +748,9 @@ constexpr std::array<BatchSweepLaunch, sizeof...(F)> batch_sweep_row(std::intege
     return {&batch_sweep_one<VEC, BF16, F>...};
 }
 
-constexpr int kFlagCombos = 16;  // template flag bits of the batched sweep
-constexpr int kSweepCombos = 32; // plus the fused-residual bit for the single-grid sweep
-using FlagSeq = std::make_integer_sequence<int, kFlagCombos>;
+constexpr int kSweepCombos = 32;  // the template flag bits plus the fused-residual bit
 using SweepFlagSeq = std::make_integer_sequence<int, kSweepCombos>;
 static_assert((kTemplateFlagMask | kFlagFuseResidual) < kSweepCombos, "sweep launcher table too small");
-static_assert(kTemplateFlagMask < kFlagCombos, "batched sweep launcher table too small");
 
 int vec_index(int vec) { return vec == 1 ? 0 : (vec == 2 ? 1 : 2); }
 
@@ -734,12 +763,12 @@ SweepLaunch sweep_launcher(int vec, bool bf16, int flags) {
 }
 
 BatchSweepLaunch batch_sweep_launcher(int vec, bool bf16, int flags) {
-    static const std::array<BatchSweepLaunch, kFlagCombos> table[2][3] = {
-        {batch_sweep_row<1, false>(FlagSeq{}), batch_sweep_row<2, false>(FlagSeq{}),
-         batch_sweep_row<4, false>(FlagSeq{})},
-        {batch_sweep_row<1, true>(FlagSeq{}), batch_sweep_row<2, true>(FlagSeq{}),
-         batch_sweep_row<4, true>(FlagSeq{})}};
-    return table[bf16 ? 1 : 0][vec_index(vec)][flags & (kFlagCombos - 1)];
+    static const std::array<BatchSweepLaunch, kSweepCombos> table[2][3] = {
+        {batch_sweep_row<1, false>(SweepFlagSeq{}), batch_sweep_row<2, false>(SweepFlagSeq{}),
+         batch_sweep_row<4, false>(SweepFlagSeq{})},
+        {batch_sweep_row<1, true>(SweepFlagSeq{}), batch_sweep_row<2, true>(SweepFlagSeq{}),
+         batch_sweep_row<4, true>(SweepFlagSeq{})}};
+    return table[bf16 ? 1 : 0][vec_index(vec)][flags & (kSweepCombos - 1)];
 }
 
 }  // namespace
@@ -785,10 +814,16 @@ void launch_finalize(const double *partials, long long n, float omega, double *g
 }
 
 void launch_batch_sweep(const GridView *views, const SweepItem *items, int nitems, const TileCfg &t, int bf16,
-                        float omega, int grid_blocks, hipStream_t s) {
-    batch_sweep_launcher(t.vec, bf16 != 0, t.flags & kTemplateFlagMask)(views, items, nitems, t, omega, grid_blocks,
-                                                                          s);
+                        float omega, int grid_blocks, hipStream_t s, double *fused_parts) {
+    const int flags = (t.flags & kTemplateFlagMask) | (fused_parts ? kFlagFuseResidual : 0);
+    batch_sweep_launcher(t.vec, bf16 != 0, flags)(views, items, nitems, t, omega, grid_blocks, fused_parts, s);
     check_launch("batched sweep kernel launch");
+}
+
+void launch_batch_finalize_parts(const GridView *views, const double *parts, const long long *range, int ngrids,
+                                 float omega, hipStream_t s) {
+    batch_finalize_parts_kernel<<<ngrids, kResidualThreads, 0, s>>>(views, parts, range, static_cast<double>(omega));
+    check_launch("batched fused finalize launch");
 }
 
 static int rows_per_wave(int nrt, int blocks) {

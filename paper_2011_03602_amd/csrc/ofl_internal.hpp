@@ -110,8 +110,11 @@ void launch_fill_zero(void *ptr, size_t bytes, hipStream_t s);
 void launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 
 // Batched launches (kernels.hip).
+// fused_parts != nullptr: fuse the residual, rows partials per item (slot item*rows + wave).
 void launch_batch_sweep(const GridView *views, const SweepItem *items, int nitems, const TileCfg &t, int bf16,
-                        float omega, int grid_blocks, hipStream_t s);
+                        float omega, int grid_blocks, hipStream_t s, double *fused_parts = nullptr);
+void launch_batch_finalize_parts(const GridView *views, const double *parts, const long long *range, int ngrids,
+                                 float omega, hipStream_t s);
 void launch_batch_residual(const GridView *views, const RowItem *items, int nitems, int vec, int sum_mode, int flags,
                            int grid_blocks, hipStream_t s);
 void launch_batch_finalize(const GridView *views, const int *partial_range, int ngrids, float omega,

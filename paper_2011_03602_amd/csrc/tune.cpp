@@ -268,6 +268,7 @@ double time_batch(ofl_batch *b, const TileCfg &t, const ofl_ga_params &ga) {
     batch_build_tables(b);
     batch_launch(b, ga.probe_iters, kCheckOmega);  // warm-up (captures the graph)
     hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    batch_after_run(b, ga.probe_iters);
     EventPair ev;
     std::vector<double> ts;
     for (int r = 0; r < ga.repeats; ++r) {
@@ -275,6 +276,7 @@ double time_batch(ofl_batch *b, const TileCfg &t, const ofl_ga_params &ga) {
         batch_launch(b, ga.probe_iters, kCheckOmega);
         hip_check(hipEventRecord(ev.b, b->stream), "hipEventRecord");
         hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+        batch_after_run(b, ga.probe_iters);
         ts.push_back(ev.ms());
     }
     return median(ts);

@@ -410,6 +410,37 @@ def test_batch_per_grid_vector_width(fmt):
         g.close()
 
 
+@pytest.mark.parametrize("fusion", [ofl.OFL_FUSE_RESIDUAL, ofl.OFL_FUSE_COPYBACK_SWAP,
+                                    ofl.OFL_FUSE_RESIDUAL | ofl.OFL_FUSE_COPYBACK_SWAP])
+@pytest.mark.parametrize("fmt", [ofl.OFL_COEF_F32, ofl.OFL_COEF_BF16_OFFSET])
+def test_fused_batch_equals_unfused_batch(fusion, fmt):
+    say("fused batch", fusion, "fmt", fmt)
+    probs = _small_batch()
+    tile = ofl.tile(vec=0, rows=4, kchunk=4, flags=1)
+    ref = [ofl.Grid(a, coef_format=fmt) for a in probs]
+    rb = ofl.ofl_batch_create([g.handle for g in ref], tile)
+    r_ref = ofl.ofl_batch_run(rb, 5, OMEGA, len(ref))
+    grids = [ofl.Grid(a, coef_format=fmt) for a in probs]
+    b = ofl.ofl_batch_create([g.handle for g in grids], tile)
+    ofl.ofl_batch_set_fusion(b, fusion)
+    for g in grids:
+        ofl.ofl_data_enter(g.handle)
+    ofl.ofl_batch_run(b, 3, OMEGA, len(grids))        # odd: buffers end exchanged
+    r = ofl.ofl_batch_run(b, 2, OMEGA, len(grids))    # replay continues from there
+    for g in grids:
+        ofl.ofl_data_exit(g.handle)
+    for g, gr, x, xr in zip(grids, ref, r, r_ref):
+        assert np.array_equal(g.p, gr.p)
+        assert x == pytest.approx(xr, rel=1e-12)
+    for a, g, x in zip(probs, grids, r):
+        if fmt == ofl.OFL_COEF_F32:
+            check_against_oracle(a, g, x, 5)
+    ofl.ofl_batch_destroy(b)
+    ofl.ofl_batch_destroy(rb)
+    for g in grids + ref:
+        g.close()
+
+
 def test_batch_graph_replays_continue_the_iteration():
     say("batch graph replay")
     probs = _small_batch(4)
