@@ -127,6 +127,19 @@ TileCfg default_tile(int I) {
     return t;
 }
 
+void sweep_shape(int I, int J, int K, const TileCfg &t, int *nti, int *nfb, int *nmc) {
+    const bool march_j = (t.flags & OFL_TILE_MARCH_J) != 0;
+    *nti = itiles(I, t.vec);
+    *nfb = ((march_j ? K : J) - 2 + t.rows - 1) / t.rows;
+    *nmc = ((march_j ? J : K) - 2 + t.kchunk - 1) / t.kchunk;
+}
+
+long long sweep_waves(int I, int J, int K, const TileCfg &t) {
+    int nti, nfb, nmc;
+    sweep_shape(I, J, K, t, &nti, &nfb, &nmc);
+    return static_cast<long long>(nti) * nfb * nmc * t.rows;
+}
+
 void *grid_array_ptr(ofl_grid *g, int a) { return g->block + g->lay.off[a]; }
 
 void grid_ensure_device(ofl_grid *g) {

@@ -773,19 +773,6 @@ BatchSweepLaunch batch_sweep_launcher(int vec, bool bf16, int flags) {
 
 }  // namespace
 
-void sweep_shape(int I, int J, int K, const TileCfg &t, int *nti, int *nfb, int *nmc) {
-    const bool march_j = (t.flags & OFL_TILE_MARCH_J) != 0;
-    *nti = itiles(I, t.vec);
-    *nfb = ((march_j ? K : J) - 2 + t.rows - 1) / t.rows;
-    *nmc = ((march_j ? J : K) - 2 + t.kchunk - 1) / t.kchunk;
-}
-
-long long sweep_waves(int I, int J, int K, const TileCfg &t) {
-    int nti, nfb, nmc;
-    sweep_shape(I, J, K, t, &nti, &nfb, &nmc);
-    return static_cast<long long>(nti) * nfb * nmc * t.rows;
-}
-
 void launch_sweep(const GridView &g, const TileCfg &t, int bf16, float omega, hipStream_t s, double *fused_parts) {
     int nti, nfb, nmc;
     sweep_shape(g.I, g.J, g.K, t, &nti, &nfb, &nmc);
