@@ -13,6 +13,7 @@ host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-variants]
        [--skip-cpu-baseline] [--profile-only NAME]
+       [--config headline|masks|precision|loops]
 """
 
 from __future__ import annotations
@@ -212,6 +213,56 @@ def run_masks(ofl, steps_unused=None):
             or os.cpu_count(), "rows": rows}
 
 
+def run_loops(ofl):
+    """Per-loop genes (the region of a GPU nest opening at its k, j or i loop):
+    end-to-end times of uniform region levels at 129x129x257, both placements,
+    and the loop-gene GA at 65x65x129 against the all-CPU gene."""
+    import torch
+
+    import synth
+
+    out = {"config": "loop genes: region level per nest, mask 111", "granularity": [], "search": []}
+    I, J, K = 129, 129, 257
+    arrays = synth.make_problem(I, J, K)
+    names = {ofl.OFL_LEVEL_K: "k", ofl.OFL_LEVEL_J: "j", ofl.OFL_LEVEL_I: "i"}
+    for mode, mode_name in ((ofl.OFL_XFER_HOISTED, "hoisted"), (ofl.OFL_XFER_PER_ITER, "per-iteration")):
+        for lev in (ofl.OFL_LEVEL_K, ofl.OFL_LEVEL_J, ofl.OFL_LEVEL_I):
+            iters = 1 if (mode == ofl.OFL_XFER_PER_ITER and lev == ofl.OFL_LEVEL_I) else 5
+            g = ofl.Grid(arrays, torch_memory=True, pinned=True)
+            ofl.ofl_set_regions(g.handle, 7, [lev] * 3, mode)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ofl.ofl_jacobi_run(g.handle, iters, OMEGA)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            st = ofl.ofl_get_stats(g.handle)
+            row = {"grid": f"{I}x{J}x{K}", "level": names[lev], "placement": mode_name, "iterations": iters,
+                   "seconds": round(dt, 4), "ms_per_iteration": round(dt * 1e3 / iters, 3),
+                   "launch_regions": [int(x) for x in st.gpu_regions], "h2d": int(st.h2d_count),
+                   "d2h": int(st.d2h_count), "pcie_gb": round((st.h2d_bytes + st.d2h_bytes) / 1e9, 3)}
+            out["granularity"].append(row)
+            log(f"regions at {names[lev]}, {mode_name}: {dt:.3f} s for {iters} iterations")
+            g.close()
+    I, J, K, iters = 65, 65, 129, 5
+    arrays = synth.make_problem(I, J, K, seed=7)
+    for mode, mode_name in ((ofl.OFL_XFER_HOISTED, "hoisted"), (ofl.OFL_XFER_PER_ITER, "per-iteration")):
+        g = ofl.Grid(arrays, torch_memory=True, pinned=True)
+        t0 = time.perf_counter()
+        r = ofl.ofl_grid_search_loops(g.handle, iters, OMEGA, mode, 0.0,
+                                      ofl.ga_params(population=16, generations=12, repeats=1))
+        dt = time.perf_counter() - t0
+        out["search"].append({"grid": f"{I}x{J}x{K}", "iterations": iters, "placement": mode_name,
+                              "gene": format(r.gene, "09b"), "mask_CRS": format(r.mask, "03b"),
+                              "levels_SRC": "".join(names[r.level[n]] if (r.mask >> n) & 1 else "-" for n in range(3)),
+                              "best_ms": round(r.best_ms, 3), "all_cpu_ms": round(r.cpu_ms, 3),
+                              "speedup_vs_all_cpu_gene": round(r.cpu_ms / r.best_ms, 2), "gene_bits": r.gene_bits,
+                              "genes_scored": r.evaluated, "patterns_measured": r.patterns,
+                              "wrong": r.rejected, "timed_out": r.timed_out, "search_seconds": round(dt, 2)})
+        log(f"loop-gene search, {mode_name}: gene {r.gene:09b} in {dt:.1f} s")
+        g.close()
+    return out
+
+
 def run_precision(ofl):
     """Errors of every storage format and residual mode against the FP64
     oracle on the FP32 inputs, 257x257x513, 100 iterations."""
@@ -276,9 +327,10 @@ def main():
                     help="headline|bf16|batch|copy: run just that under a profiler, print no JSON")
     ap.add_argument("--profile-iters", type=int, default=ITERS,
                     help="iterations per step in --profile-only runs (counter passes use a few)")
-    ap.add_argument("--config", default="headline", choices=["headline", "masks", "precision"],
+    ap.add_argument("--config", default="headline", choices=["headline", "masks", "precision", "loops"],
                     help="headline: the benchmark line; masks: every gene x placement at 129x129x257; "
-                         "precision: format/residual errors vs the FP64 oracle at 257x257x513")
+                         "precision: format/residual errors vs the FP64 oracle at 257x257x513; "
+                         "loops: per-loop genes (region levels) and their GA search")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -300,6 +352,9 @@ def main():
         return
     if args.config == "precision":
         print(json.dumps(run_precision(ofl)), flush=True)
+        return
+    if args.config == "loops":
+        print(json.dumps(run_loops(ofl)), flush=True)
         return
     if args.profile_only == "copy":
         # Copy kernel of known size: calibrates the HBM byte counters.

@@ -127,6 +127,53 @@ void ofl_grid_destroy(ofl_grid *g);
  * on either side stays valid. EINVAL for bits above 2 or an unknown mode. */
 int ofl_set_offload_mask(ofl_grid *g, unsigned mask, int xfer_mode);
 
+/* ---- one gene bit per loop statement (Sec. 4.2.2) -------------------------
+ * The offloaded program's loop statements, outermost first: the iteration loop,
+ * then the k, j and i loops of each nest (S, R, C). Offloading a loop starts a
+ * GPU region there; every loop inside the region is parallel in the kernel,
+ * and the loops outside it stay on the host, which then launches one region
+ * per trip. So a GPU nest's region opens at one of three levels:
+ *   OFL_LEVEL_K  the whole nest is one launch (what ofl_set_offload_mask sets);
+ *   OFL_LEVEL_J  the host loops over k, one launch per interior plane;
+ *   OFL_LEVEL_I  the host loops over k and j, one launch per interior row.
+ * Results do not depend on the level (p is bitwise identical; gosa is summed
+ * per region, then over regions in order, both in FP64). Transfers: hoisted,
+ * they stay outside the iteration loop as for whole-nest regions; per
+ * iteration, every region copies in the rows it reads (for S, p's rows j-1..j+1
+ * of planes k-1..k+1) and copies out the rows it writes, and each residual
+ * region's FP64 sum comes back to the host, which adds them. The fused paths
+ * (ofl_set_fusion) apply only when every GPU region is a whole nest; a batch
+ * always runs whole nests. */
+enum { OFL_LEVEL_K = 0, OFL_LEVEL_J = 1, OFL_LEVEL_I = 2 };
+#define OFL_NLOOPS 10
+
+typedef struct ofl_loop_info {
+    int nest;      /* -1 for the iteration loop, else 0 S, 1 R, 2 C */
+    int level;     /* -1 for the iteration loop, else OFL_LEVEL_* */
+    int extent;    /* trip count on this grid (the iteration loop: 0, set by each run) */
+    int parallel;  /* 1 if a GPU region can open at this loop (the screen of Sec. 4.2.2):
+                      0 for the iteration loop, whose trips read what the previous one wrote */
+} ofl_loop_info;
+
+/* The loop statements of the program on this grid, OFL_NLOOPS entries in
+ * program order: index 0 the iteration loop, 1 + 3*nest + level the others.
+ * EINVAL on NULL. */
+int ofl_loop_table(const ofl_grid *g, ofl_loop_info out[OFL_NLOOPS]);
+
+/* Apply a loop gene: bit b belongs to the b-th loop of ofl_loop_table that
+ * passes the screen, in table order (9 bits here: S k,j,i, R k,j,i, C k,j,i).
+ * A nest runs on the GPU if one of its bits is 1, its region opening at the
+ * outermost such loop; bits inside an offloaded loop change nothing (they were
+ * parallel already). EINVAL for bits beyond the gene length or an unknown
+ * placement. */
+int ofl_set_loop_gene(ofl_grid *g, uint32_t gene, int xfer_mode);
+
+/* Set the regions directly: mask as in ofl_set_offload_mask, level[n] the
+ * level of nest n's region (ignored for CPU nests); and read them back.
+ * EINVAL for an unknown mask bit, level or placement. */
+int ofl_set_regions(ofl_grid *g, unsigned mask, const int level[3], int xfer_mode);
+int ofl_get_regions(const ofl_grid *g, unsigned *mask, int level[3], int *xfer_mode);
+
 /* Run iters x (S, R, C), each nest on the device its gene bit names, with the
  * transfers the planner derives (Sec. 4.2.2: a CPU-written variable that the
  * GPU reads moves host->device; a GPU-written variable the CPU references
@@ -205,6 +252,7 @@ typedef struct ofl_stats {
     uint64_t cpu_nests[3];          /* nest executions on the CPU: S, R, C */
     double kernel_ms[3];            /* summed GPU time of S, R, C (profiling on) */
     uint64_t timed_nests[3];        /* executions included in kernel_ms */
+    uint64_t gpu_regions[3];        /* GPU region launches of S, R, C (one per nest at OFL_LEVEL_K) */
 } ofl_stats;
 
 /* Profiling on: each GPU nest is bracketed by HIP events on the grid's stream
@@ -326,6 +374,31 @@ typedef struct ofl_offload_result {
     int evaluated, rejected;
 } ofl_offload_result;
 int ofl_grid_search_offload(ofl_grid *g, const ofl_ga_params *ga, int iters, float omega, ofl_offload_result *out);
+
+/* The same search over the loop gene of ofl_set_loop_gene (Sec. 4.2.2: the
+ * loops that fail the screen are left out, the rest make the gene), with the
+ * given transfer placement. Each gene runs iters iterations from the grid's
+ * current p with nothing on the device, timed end to end on the host clock;
+ * genes that open the same regions share one measurement. A result that
+ * differs from the all-CPU gene's beyond ga->tolerance gets infinite time, and
+ * so does a gene still running after time_limit_ms (<= 0: ten times the
+ * all-CPU gene's time), which is stopped there. The best gene is applied to
+ * the grid and p is restored. ESTATE inside a data region or a batch, or when
+ * no gene reproduces the all-CPU result. */
+typedef struct ofl_loop_search_result {
+    uint32_t gene;      /* best loop gene */
+    unsigned mask;      /* the regions it opens */
+    int level[3];
+    int gene_bits;      /* gene length: loops that passed the screen */
+    double best_ms;     /* its measured time */
+    double cpu_ms;      /* the all-CPU gene's time */
+    int evaluated;      /* distinct genes scored */
+    int patterns;       /* distinct region patterns measured */
+    int rejected;       /* patterns whose result was wrong */
+    int timed_out;      /* patterns stopped at the time limit */
+} ofl_loop_search_result;
+int ofl_grid_search_loops(ofl_grid *g, const ofl_ga_params *ga, int iters, float omega, int xfer_mode,
+                          double time_limit_ms, ofl_loop_search_result *out);
 
 /* ---- measurement helper ---------------------------------------------------- */
 /* Device-to-device copy of bytes (multiple of 16, 16-byte aligned pointers)

@@ -32,6 +32,8 @@ ARRAY_NAMES = ("a0", "a1", "a2", "a3", "b0", "b1", "b2", "c0", "c1", "c2", "bnd"
 COEF_NAMES = ARRAY_NAMES[:12]
 OFL_ARR_P, OFL_ARR_WRK2 = 12, 13
 OFL_FUSE_RESIDUAL, OFL_FUSE_COPYBACK_SWAP = 1, 2
+OFL_LEVEL_K, OFL_LEVEL_J, OFL_LEVEL_I = 0, 1, 2
+OFL_NLOOPS = 10
 
 _FP = ctypes.POINTER(ctypes.c_float)
 
@@ -60,7 +62,16 @@ class OflStats(ctypes.Structure):
         ("h2d_bytes", ctypes.c_uint64), ("d2h_bytes", ctypes.c_uint64),
         ("gpu_nests", ctypes.c_uint64 * 3), ("cpu_nests", ctypes.c_uint64 * 3),
         ("kernel_ms", ctypes.c_double * 3), ("timed_nests", ctypes.c_uint64 * 3),
+        ("gpu_regions", ctypes.c_uint64 * 3),
     ]
+
+
+class OflLoopInfo(ctypes.Structure):
+    _fields_ = [("nest", ctypes.c_int), ("level", ctypes.c_int), ("extent", ctypes.c_int),
+                ("parallel", ctypes.c_int)]
+
+    def as_tuple(self):
+        return (self.nest, self.level, self.extent, self.parallel)
 
 
 class OflXfer(ctypes.Structure):
@@ -92,6 +103,13 @@ class OflOffloadResult(ctypes.Structure):
                 ("cpu_ms", ctypes.c_double), ("evaluated", ctypes.c_int), ("rejected", ctypes.c_int)]
 
 
+class OflLoopSearchResult(ctypes.Structure):
+    _fields_ = [("gene", ctypes.c_uint32), ("mask", ctypes.c_uint), ("level", ctypes.c_int * 3),
+                ("gene_bits", ctypes.c_int), ("best_ms", ctypes.c_double), ("cpu_ms", ctypes.c_double),
+                ("evaluated", ctypes.c_int), ("patterns", ctypes.c_int), ("rejected", ctypes.c_int),
+                ("timed_out", ctypes.c_int)]
+
+
 OFL_GENE_EVAL = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.c_uint32, ctypes.c_void_p)
 
 
@@ -109,6 +127,11 @@ _SIGS = {
     "ofl_grid_create": ([ctypes.POINTER(OflGridDesc), ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "ofl_grid_destroy": ([ctypes.c_void_p], None),
     "ofl_set_offload_mask": ([ctypes.c_void_p, ctypes.c_uint, ctypes.c_int], ctypes.c_int),
+    "ofl_loop_table": ([ctypes.c_void_p, ctypes.POINTER(OflLoopInfo)], ctypes.c_int),
+    "ofl_set_loop_gene": ([ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int], ctypes.c_int),
+    "ofl_set_regions": ([ctypes.c_void_p, ctypes.c_uint, ctypes.POINTER(ctypes.c_int), ctypes.c_int], ctypes.c_int),
+    "ofl_get_regions": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint), ctypes.POINTER(ctypes.c_int),
+                         ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "ofl_jacobi_run": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "ofl_residual": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "ofl_data_enter": ([ctypes.c_void_p], ctypes.c_int),
@@ -137,6 +160,8 @@ _SIGS = {
                        ctypes.POINTER(OflGaResult)], ctypes.c_int),
     "ofl_grid_search_offload": ([ctypes.c_void_p, ctypes.POINTER(OflGaParams), ctypes.c_int, ctypes.c_float,
                                  ctypes.POINTER(OflOffloadResult)], ctypes.c_int),
+    "ofl_grid_search_loops": ([ctypes.c_void_p, ctypes.POINTER(OflGaParams), ctypes.c_int, ctypes.c_float,
+                               ctypes.c_int, ctypes.c_double, ctypes.POINTER(OflLoopSearchResult)], ctypes.c_int),
     "ofl_device_copy": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
     "ofl_last_error": ([], ctypes.c_char_p),
     "ofl_version": ([], ctypes.c_char_p),
@@ -189,6 +214,30 @@ def ofl_grid_destroy(g) -> None:
 
 def ofl_set_offload_mask(g, mask: int, xfer_mode: int = OFL_XFER_HOISTED) -> None:
     _check(lib().ofl_set_offload_mask(g, mask, xfer_mode))
+
+
+def ofl_loop_table(g) -> list:
+    """The program's loop statements: (nest, level, extent, parallel) per loop, in program order."""
+    t = (OflLoopInfo * OFL_NLOOPS)()
+    _check(lib().ofl_loop_table(g, t))
+    return [x.as_tuple() for x in t]
+
+
+def ofl_set_loop_gene(g, gene: int, xfer_mode: int = OFL_XFER_HOISTED) -> None:
+    _check(lib().ofl_set_loop_gene(g, gene, xfer_mode))
+
+
+def ofl_set_regions(g, mask: int, level: Sequence[int], xfer_mode: int = OFL_XFER_HOISTED) -> None:
+    lv = (ctypes.c_int * 3)(*level)
+    _check(lib().ofl_set_regions(g, mask, lv, xfer_mode))
+
+
+def ofl_get_regions(g):
+    """(mask, [level of S, R, C], xfer_mode)."""
+    mask, mode = ctypes.c_uint(), ctypes.c_int()
+    lv = (ctypes.c_int * 3)()
+    _check(lib().ofl_get_regions(g, ctypes.byref(mask), lv, ctypes.byref(mode)))
+    return mask.value, list(lv), mode.value
 
 
 def ofl_jacobi_run(g, iters: int, omega: float) -> float:
@@ -321,6 +370,14 @@ def ofl_ga_search(bits: int, evaluate, ga: Optional[OflGaParams] = None, seed_ge
     r = OflGaResult()
     _check(lib().ofl_ga_search(bits, ctypes.byref(ga) if ga is not None else None, seed_gene, cb, None,
                                ctypes.byref(r)))
+    return r
+
+
+def ofl_grid_search_loops(g, iters: int, omega: float, xfer_mode: int = OFL_XFER_HOISTED,
+                          time_limit_ms: float = 0.0, ga: Optional[OflGaParams] = None) -> OflLoopSearchResult:
+    r = OflLoopSearchResult()
+    _check(lib().ofl_grid_search_loops(g, ctypes.byref(ga) if ga is not None else None, iters, omega, xfer_mode,
+                                       time_limit_ms, ctypes.byref(r)))
     return r
 
 

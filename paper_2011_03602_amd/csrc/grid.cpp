@@ -7,6 +7,7 @@
 // transfers the planner derives from the variable reference relations (Sec.
 // 4.2.2).
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <utility>
 #include <cstring>
@@ -255,7 +256,151 @@ void gpu_nest(ofl_grid *g, int nest, float omega) {
     }
     prof_end(g);
     g->stats.gpu_nests[nest] += 1;
+    g->stats.gpu_regions[nest] += 1;
     g->pending = true;
+}
+
+void check_deadline(const ofl_grid *g) {
+    if (g->deadline_ns == 0)
+        return;
+    const long long now = std::chrono::duration_cast<std::chrono::nanoseconds>(
+                              std::chrono::steady_clock::now().time_since_epoch())
+                              .count();
+    if (now > g->deadline_ns)
+        throw Timeout{};
+}
+
+// Interior planes [k0, k1) x rows [j0, j1) of a nest split into regions.
+struct Region {
+    int k0, k1, j0, j1;
+};
+
+// The same arrays seen as the sub-box of planes k0-1..k1 and rows j0-1..j1:
+// its interior is the region, and the kernels run on it unchanged (they address
+// rows by pitch and planes by plane, which stay those of the whole grid).
+GridView region_view(const GridView &v, const Region &r, size_t coef_bytes) {
+    GridView s = v;
+    const long long off = static_cast<long long>(r.k0 - 1) * v.plane + static_cast<long long>(r.j0 - 1) * v.pitch;
+    s.p = v.p + off;
+    s.wrk2 = v.wrk2 + off;
+    for (int a = 0; a < kNCoef; ++a)
+        s.coef[a] = static_cast<const char *>(v.coef[a]) + off * static_cast<long long>(coef_bytes);
+    s.J = r.j1 - r.j0 + 2;
+    s.K = r.k1 - r.k0 + 2;
+    return s;
+}
+
+// Rows [j0, j1) of planes [k0, k1) of array a between host and device, one
+// pitched copy per plane (the host rows of a plane are contiguous).
+void xfer_box(ofl_grid *g, int a, int dir, int k0, int k1, int j0, int j1) {
+    const size_t eb = array_elem_bytes(g, a);
+    const size_t row = static_cast<size_t>(g->I) * eb;
+    const size_t dpitch = static_cast<size_t>(g->lay.pitch) * eb;
+    char *dev = static_cast<char *>(grid_array_ptr(g, a));
+    for (int k = k0; k < k1; ++k) {
+        const size_t hoff = (static_cast<size_t>(k) * g->J + j0) * row;
+        const size_t doff = (static_cast<size_t>(k) * g->lay.plane + static_cast<size_t>(j0) * g->lay.pitch) * eb;
+        if (dir == 0) {
+            const char *src = static_cast<const char *>(host_src(g, a)) + hoff;
+            hip_check(hipMemcpy2DAsync(dev + doff, dpitch, src, row, row, j1 - j0, hipMemcpyHostToDevice, g->stream),
+                      "hipMemcpy2DAsync(host->device rows)");
+        } else {
+            char *dst = reinterpret_cast<char *>(a == OFL_ARR_P ? g->p : g->wrk2) + hoff;
+            hip_check(hipMemcpy2DAsync(dst, row, dev + doff, dpitch, row, j1 - j0, hipMemcpyDeviceToHost, g->stream),
+                      "hipMemcpy2DAsync(device->host rows)");
+        }
+    }
+    const uint64_t bytes = static_cast<uint64_t>(k1 - k0) * static_cast<uint64_t>(j1 - j0) * row;
+    if (dir == 0) {
+        g->stats.h2d_count += 1;
+        g->stats.h2d_bytes += bytes;
+        if (a == OFL_ARR_P || a == OFL_ARR_WRK2)
+            g->wrk2_boundary_ok = false;
+    } else {
+        g->stats.d2h_count += 1;
+        g->stats.d2h_bytes += bytes;
+    }
+    g->pending = true;
+}
+
+// A GPU nest whose region opens below the k loop: the host runs the outer
+// loop(s) and launches the nest's kernel once per plane (OFL_LEVEL_J) or per
+// row (OFL_LEVEL_I). With per_iter, each region first copies in the rows of
+// `ins` it reads and afterwards copies out the rows of `out` it wrote, and a
+// residual region's sum comes home at once.
+void gpu_nest_regions(ofl_grid *g, int nest, float omega, bool per_iter, const std::vector<int> &ins, int out) {
+    const int lev = g->level[nest];
+    const int nk = g->K - 2, nj = g->J - 2;
+    const long long nreg = lev == OFL_LEVEL_J ? nk : static_cast<long long>(nk) * nj;
+    const size_t cb = g->lay.coef_elem;
+    if (nest == kR) {
+        if (nreg > g->region_sums_cap) {
+            grid_sync(g);
+            if (g->region_sums)
+                hip_check(hipFree(g->region_sums), "hipFree(region sums)");
+            g->region_sums = nullptr;
+            g->region_sums_cap = 0;
+            void *ptr = nullptr;
+            hip_check(hipMalloc(&ptr, sizeof(double) * static_cast<size_t>(nreg)), "hipMalloc(region sums)");
+            g->region_sums = static_cast<double *>(ptr);
+            g->region_sums_cap = nreg;
+        }
+        if (per_iter)
+            g->region_host.assign(static_cast<size_t>(nreg), 0.0);
+    }
+    if (!per_iter)
+        prof_begin(g, nest);
+    const int row_trips = lev == OFL_LEVEL_J ? 1 : nj;  // host trips of the j loop inside each k trip
+    long long idx = 0;
+    for (int k = 1; k <= nk; ++k) {
+        for (int t = 0; t < row_trips; ++t, ++idx) {
+            check_deadline(g);
+            const Region r = lev == OFL_LEVEL_J ? Region{k, k + 1, 1, g->J - 1} : Region{k, k + 1, t + 1, t + 2};
+            if (per_iter) {
+                for (int a : ins) {
+                    const bool halo = nest == kS && a == OFL_ARR_P;  // the stencil's p rows and planes
+                    // whole planes at OFL_LEVEL_J (the boundary rows ride along), rows at OFL_LEVEL_I
+                    const int j0 = lev == OFL_LEVEL_J ? 0 : (halo ? r.j0 - 1 : r.j0);
+                    const int j1 = lev == OFL_LEVEL_J ? g->J : (halo ? r.j1 + 1 : r.j1);
+                    xfer_box(g, a, 0, halo ? r.k0 - 1 : r.k0, halo ? r.k1 + 1 : r.k1, j0, j1);
+                }
+            }
+            GridView v = region_view(g->view, r, cb);
+            if (nest == kS) {
+                launch_sweep(v, g->tile, g->fmt != OFL_COEF_F32, omega, g->stream);
+            } else if (nest == kR) {
+                v.gosa = g->region_sums + idx;
+                launch_residual(v, g->tile.vec, g->sum_mode, g->tile.flags, 1.0f, g->stream);
+                if (per_iter)
+                    hip_check(hipMemcpyAsync(&g->region_host[static_cast<size_t>(idx)], v.gosa, sizeof(double),
+                                             hipMemcpyDeviceToHost, g->stream),
+                              "hipMemcpyAsync(region sum)");
+            } else {
+                launch_copyback(v, g->tile.vec, g->tile.flags, g->stream);
+            }
+            g->stats.gpu_regions[nest] += 1;
+            g->pending = true;
+            if (per_iter && out >= 0)
+                xfer_box(g, out, 1, r.k0, r.k1, lev == OFL_LEVEL_J ? 0 : r.j0, lev == OFL_LEVEL_J ? g->J : r.j1);
+        }
+    }
+    if (nest == kR) {
+        if (per_iter) {
+            grid_sync(g);
+            double sum = 0.0;
+            for (double x : g->region_host)
+                sum += x;
+            const double w = static_cast<double>(omega);
+            g->gosa_host = sum / (w * w);
+            g->gosa_on_dev = false;
+        } else {
+            launch_finalize(g->region_sums, nreg, omega, g->view.gosa, g->stream, g->view.partials, kResidualBlocks);
+            g->gosa_on_dev = true;
+        }
+    }
+    if (!per_iter)
+        prof_end(g);
+    g->stats.gpu_nests[nest] += 1;
 }
 
 void cpu_nest(ofl_grid *g, int nest, float omega) {
@@ -348,20 +493,49 @@ void run_fused(ofl_grid *g, int iters, float omega) {
 }  // namespace
 
 // The outer loop of the offloaded program: iters x (S, R[, C]).
+bool grid_whole_nests(const ofl_grid *g) {
+    for (int n = 0; n < 3; ++n)
+        if (((g->mask >> n) & 1u) && g->level[n] != OFL_LEVEL_K)
+            return false;
+    return true;
+}
+
 void grid_run_loop(ofl_grid *g, int iters, float omega, int nests) {
     if (nests == 3 && g->fusion != 0 && g->mask == OFL_MASK_ALL_GPU && g->mode == OFL_XFER_HOISTED &&
-        g->batch_refs == 0) {
+        g->batch_refs == 0 && grid_whole_nests(g)) {
         run_fused(g, iters, omega);
         return;
     }
     std::vector<Xfer> xs;
+    std::vector<int> ins;
     for (int it = 0; it < iters; ++it) {
         for (int nest = 0; nest < nests; ++nest) {
+            check_deadline(g);
             const bool gpu = ((g->mask >> nest) & 1u) != 0;
             if (gpu)
                 grid_ensure_device(g);
             xs.clear();
             plan_before(it, nest, gpu, g->mode, g->valid, xs);
+            if (gpu && g->level[nest] != OFL_LEVEL_K) {
+                // The planner's whole-array decisions stand; hoisted ones run
+                // here, outside the regions, per-iteration ones region by region.
+                const bool per_iter = g->mode == OFL_XFER_PER_ITER;
+                ins.clear();
+                if (per_iter)
+                    for (const Xfer &x : xs)
+                        ins.push_back(x.array);
+                else
+                    grid_exec(g, xs);
+                xs.clear();
+                plan_after(it, nest, gpu, g->mode, g->valid, xs);
+                int out = -1;
+                for (const Xfer &x : xs)
+                    out = x.array;  // per-iteration: the nest's written array, copied out by region
+                if (!per_iter)
+                    out = -1;
+                gpu_nest_regions(g, nest, omega, per_iter, ins, out);
+                continue;
+            }
             grid_exec(g, xs);
             if (gpu)
                 gpu_nest(g, nest, omega);
@@ -489,6 +663,61 @@ void grid_exec(ofl_grid *g, const std::vector<Xfer> &xs) {
     }
 }
 
+namespace {
+
+// The program's loop statements in order: the iteration loop, then k, j, i of S, R, C.
+void loop_table(const ofl_grid *g, ofl_loop_info *out) {
+    out[0] = {-1, -1, 0, 0};  // trip n reads the p that trip n-1 wrote: no region can open here
+    const int extent[3] = {g->K - 2, g->J - 2, g->I - 2};
+    for (int n = 0; n < 3; ++n)
+        for (int l = 0; l < 3; ++l)
+            out[1 + 3 * n + l] = {n, l, extent[l], 1};
+}
+
+void check_regions(unsigned mask, const int *level, int xfer_mode) {
+    if (mask > OFL_MASK_ALL_GPU)
+        fail(OFL_EINVAL, "mask has bits above bit 2");
+    if (xfer_mode != OFL_XFER_PER_ITER && xfer_mode != OFL_XFER_HOISTED)
+        fail(OFL_EINVAL, "unknown xfer_mode");
+    for (int n = 0; n < 3; ++n)
+        if (level[n] < OFL_LEVEL_K || level[n] > OFL_LEVEL_I)
+            fail(OFL_EINVAL, "unknown region level");
+}
+
+}  // namespace
+
+// Loop gene -> regions: the gene's bits follow the loops that pass the screen,
+// in program order; a nest's region opens at its outermost offloaded loop.
+int loop_gene_bits(const ofl_grid *g) {
+    ofl_loop_info t[OFL_NLOOPS];
+    loop_table(g, t);
+    int bits = 0;
+    for (const ofl_loop_info &x : t)
+        bits += x.parallel;
+    return bits;
+}
+
+void decode_loop_gene(const ofl_grid *g, uint32_t gene, unsigned *mask, int level[3]) {
+    ofl_loop_info t[OFL_NLOOPS];
+    loop_table(g, t);
+    *mask = 0;
+    for (int n = 0; n < 3; ++n)
+        level[n] = OFL_LEVEL_K;
+    int b = 0;
+    bool opened[3] = {false, false, false};
+    for (const ofl_loop_info &x : t) {
+        if (!x.parallel)
+            continue;
+        const bool on = ((gene >> b) & 1u) != 0;
+        b += 1;
+        if (on && !opened[x.nest]) {
+            opened[x.nest] = true;
+            *mask |= 1u << x.nest;
+            level[x.nest] = x.level;
+        }
+    }
+}
+
 }  // namespace ofl
 
 using namespace ofl;
@@ -565,6 +794,8 @@ void ofl_grid_destroy(ofl_grid *g) {
             (void)hipEventDestroy(e);
         if (g->fused_parts)
             (void)hipFree(g->fused_parts);
+        if (g->region_sums)
+            (void)hipFree(g->region_sums);
         if (g->own_block)
             (void)hipFree(g->block);
         if (g->own_stream)
@@ -581,6 +812,55 @@ int ofl_set_offload_mask(ofl_grid *g, unsigned mask, int xfer_mode) {
             fail(OFL_EINVAL, "unknown xfer_mode");
         g->mask = mask;
         g->mode = xfer_mode;
+        for (int n = 0; n < 3; ++n)
+            g->level[n] = OFL_LEVEL_K;
+    });
+}
+
+int ofl_loop_table(const ofl_grid *g, ofl_loop_info out[OFL_NLOOPS]) {
+    return guarded(nullptr, [&] {
+        if (!g || !out)
+            fail(OFL_EINVAL, "NULL argument");
+        loop_table(g, out);
+    });
+}
+
+int ofl_set_loop_gene(ofl_grid *g, uint32_t gene, int xfer_mode) {
+    return grid_call(g, [&] {
+        const int bits = loop_gene_bits(g);
+        if (bits < 32 && (gene >> bits) != 0)
+            fail(OFL_EINVAL, "gene has bits beyond the loops that pass the screen");
+        unsigned mask = 0;
+        int level[3];
+        decode_loop_gene(g, gene, &mask, level);
+        check_regions(mask, level, xfer_mode);
+        g->mask = mask;
+        g->mode = xfer_mode;
+        for (int n = 0; n < 3; ++n)
+            g->level[n] = level[n];
+    });
+}
+
+int ofl_set_regions(ofl_grid *g, unsigned mask, const int level[3], int xfer_mode) {
+    return grid_call(g, [&] {
+        if (!level)
+            fail(OFL_EINVAL, "NULL level");
+        check_regions(mask, level, xfer_mode);
+        g->mask = mask;
+        g->mode = xfer_mode;
+        for (int n = 0; n < 3; ++n)
+            g->level[n] = level[n];
+    });
+}
+
+int ofl_get_regions(const ofl_grid *g, unsigned *mask, int level[3], int *xfer_mode) {
+    return guarded(nullptr, [&] {
+        if (!g || !mask || !level || !xfer_mode)
+            fail(OFL_EINVAL, "NULL argument");
+        *mask = g->mask;
+        *xfer_mode = g->mode;
+        for (int n = 0; n < 3; ++n)
+            level[n] = g->level[n];
     });
 }
 

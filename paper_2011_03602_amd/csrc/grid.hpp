@@ -25,6 +25,7 @@ struct ofl_grid {
 
     unsigned mask = OFL_MASK_ALL_GPU;
     int mode = OFL_XFER_HOISTED;
+    int level[3] = {OFL_LEVEL_K, OFL_LEVEL_K, OFL_LEVEL_K};  // where each GPU nest's region opens
     ofl::TileCfg tile;
     bool in_region = false;
     ofl::Validity valid = ofl::fresh_validity();
@@ -60,13 +61,28 @@ struct ofl_grid {
     bool wrk2_boundary_ok = false;   // device wrk2 carries p's boundary (needed before swapping)
     unsigned swap_epoch = 0;         // bumped whenever p and wrk2 exchange device buffers
 
+    // residual nests split into regions: one FP64 sum per region
+    double *region_sums = nullptr;
+    long long region_sums_cap = 0;
+    std::vector<double> region_host;  // per-iteration placement: the sums brought home
+
+    // A search stops a run that outlives its time limit (steady clock, ns; 0 = none).
+    long long deadline_ns = 0;
+
     bool broken = false;
     int batch_refs = 0;
 };
 
 namespace ofl {
 
+// Thrown by a run that passed its grid's deadline (never crosses the C interface:
+// only a search sets deadlines, and it catches this).
+struct Timeout {};
+
 ofl::TileCfg default_tile(int I);
+bool grid_whole_nests(const ofl_grid *g);
+int loop_gene_bits(const ofl_grid *g);
+void decode_loop_gene(const ofl_grid *g, uint32_t gene, unsigned *mask, int level[3]);
 void grid_ensure_device(ofl_grid *g);
 void grid_sync(ofl_grid *g);
 void grid_exec(ofl_grid *g, const std::vector<Xfer> &xs);

@@ -405,6 +405,74 @@ ofl_ga_params defaults_or(const ofl_ga_params *ga) {
     return d;
 }
 
+// The measuring side of the offload searches: the initial iterate every run
+// starts from (nothing on the device, so each run pays the transfers its gene
+// needs), the all-CPU result (the original program) each run is checked
+// against, and end-to-end runs timed on the host clock.
+struct OffloadBench {
+    ofl_grid *g;
+    int iters;
+    float omega;
+    double tol;
+    std::vector<float> p0, p_ref;
+    double pmax = 0.0, gosa_ref = 0.0, cpu_ms = 0.0;
+    unsigned mask0;
+    int mode0;
+    int level0[3];
+
+    OffloadBench(ofl_grid *grid, int it, float w, double tolerance) : g(grid), iters(it), omega(w), tol(tolerance) {
+        std::vector<Xfer> xs;
+        plan_sync_host(-1, g->valid, xs);
+        grid_exec(g, xs);
+        grid_sync(g);
+        p0.assign(g->p, g->p + g->n);
+        mask0 = g->mask;
+        mode0 = g->mode;
+        std::copy(g->level, g->level + 3, level0);
+        const int cpu_level[3] = {OFL_LEVEL_K, OFL_LEVEL_K, OFL_LEVEL_K};
+        cpu_ms = run(OFL_MASK_ALL_CPU, cpu_level, OFL_XFER_HOISTED, &gosa_ref);
+        p_ref.assign(g->p, g->p + g->n);
+        for (float v : p_ref)
+            pmax = std::max(pmax, static_cast<double>(std::fabs(v)));
+    }
+
+    void restore() {
+        grid_sync(g);
+        std::memcpy(g->p, p0.data(), p0.size() * sizeof(float));
+        g->valid = fresh_validity();
+    }
+
+    // Put back the caller's regions (after a failure).
+    void restore_regions() {
+        g->mask = mask0;
+        g->mode = mode0;
+        std::copy(level0, level0 + 3, g->level);
+    }
+
+    double run(unsigned mask, const int level[3], int mode, double *gosa) {
+        restore();
+        g->mask = mask;
+        g->mode = mode;
+        std::copy(level, level + 3, g->level);
+        const auto t0 = std::chrono::steady_clock::now();
+        grid_run_loop(g, iters, omega, 3);
+        std::vector<Xfer> xs;
+        plan_sync_host(iters, g->valid, xs);
+        grid_exec(g, xs);
+        *gosa = grid_fetch_gosa(g);
+        const auto t1 = std::chrono::steady_clock::now();
+        return std::chrono::duration<double, std::milli>(t1 - t0).count();
+    }
+
+    // Does the last run reproduce the original program's result?
+    bool matches(double gosa) const {
+        double dmax = 0.0;
+        for (size_t t = 0; t < g->n; ++t)
+            dmax = std::max(dmax, std::fabs(static_cast<double>(g->p[t]) - p_ref[t]));
+        return dmax <= tol * std::max(pmax, 1e-300) && std::fabs(gosa - gosa_ref) <= 10.0 * tol * std::fabs(gosa_ref);
+    }
+};
+
 }  // namespace
 
 }  // namespace ofl
@@ -441,74 +509,141 @@ int ofl_grid_search_offload(ofl_grid *g, const ofl_ga_params *ga_in, int iters, 
             fail(OFL_ESTATE, "close the data region and leave any batch before searching offload genes");
         const ofl_ga_params ga = defaults_or(ga_in);
         check_params(ga);
-        // Bring p home, keep the initial iterate; every measurement starts from it
-        // with nothing on the device, so it includes the transfers its gene needs.
-        {
-            std::vector<Xfer> xs;
-            plan_sync_host(-1, g->valid, xs);
-            grid_exec(g, xs);
-            grid_sync(g);
-        }
-        const std::vector<float> p0(g->p, g->p + g->n);
-        const unsigned mask0 = g->mask;
-        const int mode0 = g->mode;
-        auto restore = [&] {
-            grid_sync(g);
-            std::memcpy(g->p, p0.data(), p0.size() * sizeof(float));
-            g->valid = fresh_validity();
-        };
-        auto timed_run = [&](unsigned mask, int mode, double *gosa) {
-            restore();
-            g->mask = mask;
-            g->mode = mode;
-            const auto t0 = std::chrono::steady_clock::now();
-            grid_run_loop(g, iters, omega, 3);
-            std::vector<Xfer> xs;
-            plan_sync_host(iters, g->valid, xs);
-            grid_exec(g, xs);
-            *gosa = grid_fetch_gosa(g);
-            const auto t1 = std::chrono::steady_clock::now();
-            return std::chrono::duration<double, std::milli>(t1 - t0).count();
-        };
-        // The original program: every nest on the CPU. Its result is the reference.
-        double gosa_ref = 0.0;
-        const double cpu_ms = timed_run(OFL_MASK_ALL_CPU, OFL_XFER_HOISTED, &gosa_ref);
-        const std::vector<float> p_ref(g->p, g->p + g->n);
-        double pmax = 0.0;
-        for (float v : p_ref)
-            pmax = std::max(pmax, static_cast<double>(std::fabs(v)));
+        OffloadBench bench(g, iters, omega, ga.tolerance);
+        const int whole[3] = {OFL_LEVEL_K, OFL_LEVEL_K, OFL_LEVEL_K};
         auto evaluate = [&](uint32_t gene) -> double {
             const unsigned mask = gene & 7u;
             const int mode = (gene >> 3) & 1u ? OFL_XFER_HOISTED : OFL_XFER_PER_ITER;
             double gosa = 0.0;
-            const double ms = timed_run(mask, mode, &gosa);
-            double dmax = 0.0;
-            for (size_t t = 0; t < g->n; ++t)
-                dmax = std::max(dmax, std::fabs(static_cast<double>(g->p[t]) - p_ref[t]));
-            const bool ok = dmax <= ga.tolerance * std::max(pmax, 1e-300) &&
-                            std::fabs(gosa - gosa_ref) <= 10.0 * ga.tolerance * std::fabs(gosa_ref);
-            return ok ? ms : kInf;
+            const double ms = bench.run(mask, whole, mode, &gosa);
+            return bench.matches(gosa) ? ms : kInf;
         };
         GaOutcome r;
         try {
             r = ga_search(ga, 4, OFL_MASK_ALL_GPU | 8u, evaluate);
         } catch (...) {
-            restore();
-            g->mask = mask0;
-            g->mode = mode0;
+            bench.restore();
+            bench.restore_regions();
             throw;
         }
-        restore();
-        if (!(r.best_t < kInf))
+        bench.restore();
+        if (!(r.best_t < kInf)) {
+            bench.restore_regions();
             fail(OFL_ESTATE, "no offload gene reproduced the all-CPU result");
+        }
         g->mask = r.best & 7u;
         g->mode = (r.best >> 3) & 1u ? OFL_XFER_HOISTED : OFL_XFER_PER_ITER;
+        std::copy(whole, whole + 3, g->level);
         out->mask = g->mask;
         out->xfer_mode = g->mode;
         out->best_ms = r.best_t;
-        out->cpu_ms = cpu_ms;
+        out->cpu_ms = bench.cpu_ms;
         out->evaluated = r.evaluated;
         out->rejected = r.rejected;
+    });
+}
+
+int ofl_grid_search_loops(ofl_grid *g, const ofl_ga_params *ga_in, int iters, float omega, int xfer_mode,
+                          double time_limit_ms, ofl_loop_search_result *out) {
+    return guarded(nullptr, [&] {
+        if (!g || !out)
+            fail(OFL_EINVAL, "NULL argument");
+        if (g->broken)
+            fail(OFL_EDEVICE, "grid handle unusable after an earlier device error");
+        if (iters < 1 || !std::isfinite(omega) || omega == 0.f)
+            fail(OFL_EINVAL, "iters must be >= 1 and omega finite and non-zero");
+        if (xfer_mode != OFL_XFER_PER_ITER && xfer_mode != OFL_XFER_HOISTED)
+            fail(OFL_EINVAL, "unknown xfer_mode");
+        if (!(time_limit_ms == time_limit_ms))
+            fail(OFL_EINVAL, "time_limit_ms is NaN");
+        if (g->in_region || g->batch_refs > 0)
+            fail(OFL_ESTATE, "close the data region and leave any batch before searching loop genes");
+        const ofl_ga_params ga = defaults_or(ga_in);
+        check_params(ga);
+        const int bits = loop_gene_bits(g);
+        OffloadBench bench(g, iters, omega, ga.tolerance);
+        const double limit_ms = time_limit_ms > 0.0 ? time_limit_ms : 10.0 * bench.cpu_ms;
+        // Genes that open the same regions are one program: measure it once.
+        std::map<uint32_t, double> measured;
+        int wrong = 0, timed_out = 0;
+        auto evaluate = [&](uint32_t gene) -> double {
+            unsigned mask = 0;
+            int level[3];
+            decode_loop_gene(g, gene, &mask, level);
+            uint32_t key = mask;
+            for (int n = 0; n < 3; ++n)
+                if ((mask >> n) & 1u)
+                    key |= static_cast<uint32_t>(level[n]) << (3 + 2 * n);
+            const auto hit = measured.find(key);
+            if (hit != measured.end())
+                return hit->second;
+            const long long start = std::chrono::duration_cast<std::chrono::nanoseconds>(
+                                        std::chrono::steady_clock::now().time_since_epoch())
+                                        .count();
+            g->deadline_ns = start + static_cast<long long>(limit_ms * 1e6);
+            double t = kInf;
+            try {
+                double gosa = 0.0;
+                const double ms = bench.run(mask, level, xfer_mode, &gosa);
+                g->deadline_ns = 0;
+                if (bench.matches(gosa))
+                    t = ms;
+                else
+                    wrong += 1;
+            } catch (const Timeout &) {
+                g->deadline_ns = 0;
+                grid_sync(g);
+                timed_out += 1;
+            } catch (...) {
+                g->deadline_ns = 0;
+                throw;
+            }
+            measured[key] = t;
+            return t;
+        };
+        // The original gene offloads every nest whole: each nest's k loop.
+        uint32_t seed_gene = 0;
+        {
+            ofl_loop_info t[OFL_NLOOPS];
+            ofl_loop_table(g, t);
+            int b = 0;
+            for (const ofl_loop_info &x : t) {
+                if (!x.parallel)
+                    continue;
+                if (x.level == OFL_LEVEL_K)
+                    seed_gene |= 1u << b;
+                b += 1;
+            }
+        }
+        GaOutcome r;
+        try {
+            r = ga_search(ga, bits, seed_gene, evaluate);
+        } catch (...) {
+            bench.restore();
+            bench.restore_regions();
+            throw;
+        }
+        bench.restore();
+        if (!(r.best_t < kInf)) {
+            bench.restore_regions();
+            fail(OFL_ESTATE, "no loop gene reproduced the all-CPU result within the time limit");
+        }
+        unsigned mask = 0;
+        int level[3];
+        decode_loop_gene(g, r.best, &mask, level);
+        g->mask = mask;
+        g->mode = xfer_mode;
+        std::copy(level, level + 3, g->level);
+        out->gene = r.best;
+        out->mask = mask;
+        std::copy(level, level + 3, out->level);
+        out->gene_bits = bits;
+        out->best_ms = r.best_t;
+        out->cpu_ms = bench.cpu_ms;
+        out->evaluated = r.evaluated;
+        out->patterns = static_cast<int>(measured.size());
+        out->rejected = wrong;
+        out->timed_out = timed_out;
     });
 }
 

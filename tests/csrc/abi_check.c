@@ -194,6 +194,42 @@ int main(void) {
         CHECK(ofl_plan(7, 1, 1, 1, hv, dv, NULL, 0, &count) == OFL_EINVAL);
     }
 
+    /* the loop table, every loop gene, region settings */
+    {
+        problem q;
+        make(&q, 9, 7, 6);
+        ofl_grid_desc dq = desc_of(&q, 0, 0);
+        ofl_grid *gq = NULL;
+        CHECK(ofl_grid_create(&dq, &gq) == OFL_OK);
+        ofl_loop_info t[OFL_NLOOPS];
+        CHECK(ofl_loop_table(gq, t) == OFL_OK && t[0].parallel == 0 && t[0].nest == -1);
+        for (int l = 1; l < OFL_NLOOPS; ++l)
+            CHECK(t[l].parallel == 1 && t[l].nest == (l - 1) / 3 && t[l].level == (l - 1) % 3);
+        for (uint32_t gene = 0; gene < 512; ++gene) {
+            unsigned mask = 99;
+            int lev[3] = {-7, -7, -7}, mode = -7;
+            CHECK(ofl_set_loop_gene(gq, gene, OFL_XFER_PER_ITER) == OFL_OK);
+            CHECK(ofl_get_regions(gq, &mask, lev, &mode) == OFL_OK && mode == OFL_XFER_PER_ITER);
+            for (int n = 0; n < 3; ++n) {
+                unsigned bits = (gene >> (3 * n)) & 7u;
+                CHECK(((mask >> n) & 1u) == (bits != 0));
+                if (bits)
+                    CHECK(lev[n] == __builtin_ctz(bits));
+            }
+        }
+        CHECK(ofl_set_loop_gene(gq, 512u, OFL_XFER_HOISTED) == OFL_EINVAL);
+        int lv[3] = {2, 1, 2};
+        CHECK(ofl_set_regions(gq, 0u, lv, OFL_XFER_HOISTED) == OFL_OK);
+        double gs = 0.0;
+        CHECK(ofl_jacobi_run(gq, 2, 0.8f, &gs) == OFL_OK && isfinite(gs));
+        lv[1] = 3;
+        CHECK(ofl_set_regions(gq, 7u, lv, OFL_XFER_HOISTED) == OFL_EINVAL);
+        CHECK(ofl_set_regions(gq, 7u, NULL, OFL_XFER_HOISTED) == OFL_EINVAL);
+        CHECK(ofl_loop_table(NULL, t) == OFL_EINVAL);
+        ofl_grid_destroy(gq);
+        drop(&q);
+    }
+
     /* the GA on a synthetic landscape */
     uint32_t target = 0x5au;
     ofl_ga_params ga = {16, 15, 7ull, 0.9, 0.08, 1, 1, 1, 1e-5};

@@ -1,0 +1,175 @@
+"""GPU parity of nests split into regions (a loop gene whose GPU region opens
+below a nest's k loop, Sec. 4.2.2): every level combination and placement
+against the whole-nest runs (p bitwise, residual to FP64 rounding) and the
+FP64 oracle, the transfer and launch counts each placement implies, mixed
+CPU/GPU genes, bfloat16 storage, and the loop-gene search."""
+
+import sys
+from itertools import product
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2011_03602_amd as ofl
+import synth
+from helpers import OMEGA, TOL_BF16, TOL_GOSA_F32, TOL_P_F32, boundary_equal, p_rel_err, rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # collected on CPU hosts, skipped there
+    pytestmark = [pytest.mark.gpu, pytest.mark.skip(reason="needs a GPU")]
+
+ITERS = 4
+SHAPE = (300, 8, 6)  # two i-tiles at vector width 4, a ragged tail; 4 x 6 interior rows
+
+
+def say(*args):
+    print("[gpu]", *args, flush=True)
+    sys.stdout.flush()
+
+
+def regions_per_nest(level, I, J, K):
+    return {ofl.OFL_LEVEL_K: 1, ofl.OFL_LEVEL_J: K - 2, ofl.OFL_LEVEL_I: (K - 2) * (J - 2)}[level]
+
+
+@pytest.fixture(scope="module")
+def case():
+    a = synth.make_problem(*SHAPE, seed=31)
+    ref = oracle.jacobi(a, ITERS, float(OMEGA))
+    g = ofl.Grid(a)
+    ofl.ofl_set_offload_mask(g.handle, 7, ofl.OFL_XFER_HOISTED)
+    gosa = ofl.ofl_jacobi_run(g.handle, ITERS, OMEGA)
+    whole = (g.p.copy(), gosa)
+    g.close()
+    return a, ref, whole
+
+
+@pytest.mark.parametrize("mode", [ofl.OFL_XFER_HOISTED, ofl.OFL_XFER_PER_ITER])
+@pytest.mark.parametrize("levels", list(product(range(3), repeat=3)), ids=lambda v: "".join("kji"[x] for x in v))
+def test_every_region_level_matches_whole_nests(case, levels, mode):
+    say("regions", levels, "mode", mode, "shape", SHAPE)
+    a, ref, (p_whole, gosa_whole) = case
+    I, J, K = SHAPE
+    g = ofl.Grid(a)
+    ofl.ofl_set_regions(g.handle, 7, list(levels), mode)
+    gosa = ofl.ofl_jacobi_run(g.handle, ITERS, OMEGA)
+    assert np.array_equal(g.p, p_whole)
+    assert rel_err(gosa, gosa_whole) <= 1e-12
+    assert p_rel_err(g.p, ref[0]) <= TOL_P_F32 and rel_err(gosa, ref[1]) <= TOL_GOSA_F32
+    assert boundary_equal(g.p, a["p"])
+    s = ofl.ofl_get_stats(g.handle)
+    nreg = [regions_per_nest(lv, I, J, K) for lv in levels]
+    assert list(s.gpu_regions) == [ITERS * n for n in nreg]
+    assert list(s.gpu_nests) == [ITERS] * 3 and list(s.cpu_nests) == [0] * 3
+    if mode == ofl.OFL_XFER_HOISTED:
+        assert (s.h2d_count, s.d2h_count) == (13, 1)
+    else:
+        # every region copies in what it reads and out what it writes: S 13 + 1, R 2, C 2 + 1
+        assert s.h2d_count == ITERS * (13 * nreg[0] + 2 * nreg[1] + 2 * nreg[2])
+        assert s.d2h_count == ITERS * (nreg[0] + nreg[2])
+    g.close()
+
+
+@pytest.mark.parametrize("mode", [ofl.OFL_XFER_HOISTED, ofl.OFL_XFER_PER_ITER])
+@pytest.mark.parametrize("mask,levels", [(1, [2, 0, 0]), (3, [1, 2, 0]), (6, [0, 1, 2]), (5, [1, 0, 2]),
+                                         (4, [0, 0, 1]), (2, [0, 2, 0])])
+def test_mixed_genes_with_split_regions(case, mask, levels, mode):
+    say("mixed gene", mask, levels, "mode", mode)
+    a, ref, (p_whole, _) = case
+    g = ofl.Grid(a)
+    ofl.ofl_set_regions(g.handle, mask, levels, mode)
+    gosa = ofl.ofl_jacobi_run(g.handle, ITERS, OMEGA)
+    assert p_rel_err(g.p, ref[0]) <= TOL_P_F32 and rel_err(gosa, ref[1]) <= TOL_GOSA_F32
+    assert boundary_equal(g.p, a["p"])
+    s = ofl.ofl_get_stats(g.handle)
+    for n in range(3):
+        assert s.gpu_nests[n] == (ITERS if (mask >> n) & 1 else 0)
+        assert s.cpu_nests[n] == (0 if (mask >> n) & 1 else ITERS)
+    g.close()
+
+
+@pytest.mark.parametrize("mode", [ofl.OFL_XFER_HOISTED, ofl.OFL_XFER_PER_ITER])
+def test_bf16_offset_regions_match_whole_nests(mode):
+    say("bf16-offset regions, mode", mode)
+    a = synth.make_problem(131, 9, 8, seed=5)
+    outs = []  # (gosa, p) per level combination
+    for levels in ([0, 0, 0], [1, 2, 1], [2, 1, 2]):
+        g = ofl.Grid(a, coef_format=ofl.OFL_COEF_BF16_OFFSET)
+        ofl.ofl_set_regions(g.handle, 7, levels, mode)
+        gosa = ofl.ofl_jacobi_run(g.handle, 3, OMEGA)
+        outs.append((gosa, g.p.copy()))
+        g.close()
+    for gosa, p in outs[1:]:
+        assert np.array_equal(p, outs[0][1]) and rel_err(gosa, outs[0][0]) <= 1e-12
+    p_ref, g_ref = oracle.jacobi(a, 3, float(OMEGA))
+    assert p_rel_err(outs[0][1], p_ref) <= TOL_BF16 and rel_err(outs[0][0], g_ref) <= TOL_BF16
+
+
+def test_residual_entry_point_with_split_regions():
+    say("ofl_residual with regions")
+    a = synth.make_problem(70, 11, 9, seed=8)
+    r_ref = oracle.residual(a)
+    for levels in ([0, 0, 0], [1, 1, 0], [2, 2, 0]):
+        for mode in (ofl.OFL_XFER_HOISTED, ofl.OFL_XFER_PER_ITER):
+            g = ofl.Grid(a)
+            ofl.ofl_set_regions(g.handle, 7, levels, mode)
+            r = ofl.ofl_residual(g.handle)
+            assert rel_err(r, r_ref) <= TOL_GOSA_F32, (levels, mode)
+            assert np.array_equal(g.p, a["p"])
+            g.close()
+
+
+def test_split_runs_in_a_data_region():
+    say("regions inside a data region")
+    a = synth.make_problem(*SHAPE, seed=31)
+    g = ofl.Grid(a)
+    ofl.ofl_set_regions(g.handle, 7, [1, 2, 1], ofl.OFL_XFER_HOISTED)
+    ofl.ofl_data_enter(g.handle)
+    ofl.ofl_jacobi_run(g.handle, 2, OMEGA)
+    ofl.ofl_set_regions(g.handle, 7, [2, 0, 2], ofl.OFL_XFER_HOISTED)
+    gosa = ofl.ofl_jacobi_run(g.handle, 2, OMEGA)
+    ofl.ofl_data_exit(g.handle)
+    p_ref, g_ref = oracle.jacobi(a, 4, float(OMEGA))
+    assert p_rel_err(g.p, p_ref) <= TOL_P_F32 and rel_err(gosa, g_ref) <= TOL_GOSA_F32
+    s = ofl.ofl_get_stats(g.handle)
+    assert (s.h2d_count, s.d2h_count) == (13, 1)
+    g.close()
+
+
+@pytest.mark.parametrize("mode", [ofl.OFL_XFER_HOISTED, ofl.OFL_XFER_PER_ITER])
+def test_loop_gene_search(mode):
+    say("loop gene GA, mode", mode)
+    a = synth.make_problem(66, 35, 40, seed=23)
+    g = ofl.Grid(a)
+    r = ofl.ofl_grid_search_loops(g.handle, 3, OMEGA, mode, 0.0,
+                                  ofl.ga_params(population=8, generations=4, seed=11))
+    assert r.gene_bits == 9 and 1 <= r.patterns <= r.evaluated
+    assert r.best_ms > 0 and r.cpu_ms > 0
+    assert r.rejected == 0
+    assert np.array_equal(g.p, a["p"])  # the search leaves the iterate alone
+    mask, levels, m = ofl.ofl_get_regions(g.handle)
+    assert (mask, m) == (r.mask, mode)
+    assert [levels[n] for n in range(3) if (mask >> n) & 1] == [r.level[n] for n in range(3) if (mask >> n) & 1]
+    gosa = ofl.ofl_jacobi_run(g.handle, 3, OMEGA)
+    p_ref, g_ref = oracle.jacobi(a, 3, float(OMEGA))
+    assert p_rel_err(g.p, p_ref) <= TOL_P_F32 and rel_err(gosa, g_ref) <= TOL_GOSA_F32
+    g.close()
+
+
+def test_loop_gene_search_time_limit_stops_every_gene():
+    say("loop gene GA, time limit forced from the host")
+    a = synth.make_problem(40, 20, 20, seed=3)
+    g = ofl.Grid(a)
+    ofl.ofl_set_regions(g.handle, 5, [1, 0, 2], ofl.OFL_XFER_PER_ITER)
+    with pytest.raises(ofl.OflError) as e:
+        ofl.ofl_grid_search_loops(g.handle, 2, OMEGA, ofl.OFL_XFER_HOISTED, 1e-6,
+                                  ofl.ga_params(population=4, generations=2, seed=2))
+    assert e.value.code == ofl.OFL_ESTATE
+    assert ofl.ofl_get_regions(g.handle) == (5, [1, 0, 2], ofl.OFL_XFER_PER_ITER)
+    assert np.array_equal(g.p, a["p"])
+    gosa = ofl.ofl_jacobi_run(g.handle, 2, OMEGA)  # the handle still works
+    p_ref, g_ref = oracle.jacobi(a, 2, float(OMEGA))
+    assert p_rel_err(g.p, p_ref) <= TOL_P_F32 and rel_err(gosa, g_ref) <= TOL_GOSA_F32
+    g.close()
