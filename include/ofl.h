@@ -361,7 +361,8 @@ int ofl_ga_search(int bits, const ofl_ga_params *ga, uint32_t seed_gene, ofl_gen
 /* The paper's loop-offload search (Sec. 3.2.1, Sec. 4.2.2) on one grid: the
  * gene is the 3-bit offload mask plus one bit for the transfer placement
  * (bit 3: 1 = hoisted). Each gene runs iters iterations from the grid's current
- * p with nothing on the device, end to end (transfers included, host clock);
+ * p with nothing on the device, end to end (transfers included, host clock,
+ * median of ga->repeats runs);
  * a result that differs from the all-CPU gene's (the original program) beyond
  * ga->tolerance gets infinite time. The best gene is applied to the grid and
  * p is restored. Needs a GPU for genes with GPU nests. ESTATE inside a data
@@ -378,11 +379,12 @@ int ofl_grid_search_offload(ofl_grid *g, const ofl_ga_params *ga, int iters, flo
 /* The same search over the loop gene of ofl_set_loop_gene (Sec. 4.2.2: the
  * loops that fail the screen are left out, the rest make the gene), with the
  * given transfer placement. Each gene runs iters iterations from the grid's
- * current p with nothing on the device, timed end to end on the host clock;
+ * current p with nothing on the device, timed end to end on the host clock
+ * (median of ga->repeats runs);
  * genes that open the same regions share one measurement. A result that
  * differs from the all-CPU gene's beyond ga->tolerance gets infinite time, and
- * so does a gene still running after time_limit_ms (<= 0: ten times the
- * all-CPU gene's time), which is stopped there. The best gene is applied to
+ * so does a gene with a run still going after time_limit_ms (<= 0: ten
+ * times the all-CPU gene's time), which is stopped there. The best gene is applied to
  * the grid and p is restored. ESTATE inside a data region or a batch, or when
  * no gene reproduces the all-CPU result. */
 typedef struct ofl_loop_search_result {

@@ -414,13 +414,15 @@ struct OffloadBench {
     int iters;
     float omega;
     double tol;
+    int repeats;
     std::vector<float> p0, p_ref;
     double pmax = 0.0, gosa_ref = 0.0, cpu_ms = 0.0;
     unsigned mask0;
     int mode0;
     int level0[3];
 
-    OffloadBench(ofl_grid *grid, int it, float w, double tolerance) : g(grid), iters(it), omega(w), tol(tolerance) {
+    OffloadBench(ofl_grid *grid, int it, float w, double tolerance, int reps)
+        : g(grid), iters(it), omega(w), tol(tolerance), repeats(reps) {
         std::vector<Xfer> xs;
         plan_sync_host(-1, g->valid, xs);
         grid_exec(g, xs);
@@ -449,19 +451,34 @@ struct OffloadBench {
         std::copy(level0, level0 + 3, g->level);
     }
 
-    double run(unsigned mask, const int level[3], int mode, double *gosa) {
-        restore();
-        g->mask = mask;
-        g->mode = mode;
-        std::copy(level, level + 3, g->level);
-        const auto t0 = std::chrono::steady_clock::now();
-        grid_run_loop(g, iters, omega, 3);
-        std::vector<Xfer> xs;
-        plan_sync_host(iters, g->valid, xs);
-        grid_exec(g, xs);
-        *gosa = grid_fetch_gosa(g);
-        const auto t1 = std::chrono::steady_clock::now();
-        return std::chrono::duration<double, std::milli>(t1 - t0).count();
+    // Median of `repeats` end-to-end runs, each from the initial iterate; the
+    // result of the last run stays in p and *gosa. With limit_ms > 0 a run
+    // still going after limit_ms throws Timeout.
+    double run(unsigned mask, const int level[3], int mode, double *gosa, double limit_ms = 0.0) {
+        struct ClearDeadline {
+            ofl_grid *g;
+            ~ClearDeadline() { g->deadline_ns = 0; }
+        } clear{g};
+        std::vector<double> ms;
+        for (int r = 0; r < repeats; ++r) {
+            restore();
+            g->mask = mask;
+            g->mode = mode;
+            std::copy(level, level + 3, g->level);
+            const auto t0 = std::chrono::steady_clock::now();
+            if (limit_ms > 0.0)
+                g->deadline_ns = std::chrono::duration_cast<std::chrono::nanoseconds>(t0.time_since_epoch()).count() +
+                                 static_cast<long long>(limit_ms * 1e6);
+            grid_run_loop(g, iters, omega, 3);
+            std::vector<Xfer> xs;
+            plan_sync_host(iters, g->valid, xs);
+            grid_exec(g, xs);
+            *gosa = grid_fetch_gosa(g);
+            const auto t1 = std::chrono::steady_clock::now();
+            ms.push_back(std::chrono::duration<double, std::milli>(t1 - t0).count());
+        }
+        std::sort(ms.begin(), ms.end());
+        return ms[ms.size() / 2];
     }
 
     // Does the last run reproduce the original program's result?
@@ -509,7 +526,7 @@ int ofl_grid_search_offload(ofl_grid *g, const ofl_ga_params *ga_in, int iters, 
             fail(OFL_ESTATE, "close the data region and leave any batch before searching offload genes");
         const ofl_ga_params ga = defaults_or(ga_in);
         check_params(ga);
-        OffloadBench bench(g, iters, omega, ga.tolerance);
+        OffloadBench bench(g, iters, omega, ga.tolerance, ga.repeats);
         const int whole[3] = {OFL_LEVEL_K, OFL_LEVEL_K, OFL_LEVEL_K};
         auto evaluate = [&](uint32_t gene) -> double {
             const unsigned mask = gene & 7u;
@@ -561,7 +578,7 @@ int ofl_grid_search_loops(ofl_grid *g, const ofl_ga_params *ga_in, int iters, fl
         const ofl_ga_params ga = defaults_or(ga_in);
         check_params(ga);
         const int bits = loop_gene_bits(g);
-        OffloadBench bench(g, iters, omega, ga.tolerance);
+        OffloadBench bench(g, iters, omega, ga.tolerance, ga.repeats);
         const double limit_ms = time_limit_ms > 0.0 ? time_limit_ms : 10.0 * bench.cpu_ms;
         // Genes that open the same regions are one program: measure it once.
         std::map<uint32_t, double> measured;
@@ -577,26 +594,17 @@ int ofl_grid_search_loops(ofl_grid *g, const ofl_ga_params *ga_in, int iters, fl
             const auto hit = measured.find(key);
             if (hit != measured.end())
                 return hit->second;
-            const long long start = std::chrono::duration_cast<std::chrono::nanoseconds>(
-                                        std::chrono::steady_clock::now().time_since_epoch())
-                                        .count();
-            g->deadline_ns = start + static_cast<long long>(limit_ms * 1e6);
             double t = kInf;
             try {
                 double gosa = 0.0;
-                const double ms = bench.run(mask, level, xfer_mode, &gosa);
-                g->deadline_ns = 0;
+                const double ms = bench.run(mask, level, xfer_mode, &gosa, limit_ms);
                 if (bench.matches(gosa))
                     t = ms;
                 else
                     wrong += 1;
             } catch (const Timeout &) {
-                g->deadline_ns = 0;
                 grid_sync(g);
                 timed_out += 1;
-            } catch (...) {
-                g->deadline_ns = 0;
-                throw;
             }
             measured[key] = t;
             return t;
