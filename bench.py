@@ -260,7 +260,60 @@ def run_loops(ofl):
                               "wrong": r.rejected, "timed_out": r.timed_out, "search_seconds": round(dt, 2)})
         log(f"loop-gene search, {mode_name}: gene {r.gene:09b} in {dt:.1f} s")
         g.close()
+    out["frontend"] = run_frontend(ofl)
     return out
+
+
+FRONTEND_PROGRAM = os.path.join(ROOT, "tests", "programs", "relax.py")
+
+
+def run_frontend(ofl):
+    """The same Jacobi program written in Python with its own names, read by the
+    front end and offloaded through the library: analysis time, end-to-end runs
+    against the direct interface, and the interpreted program's own rate."""
+    import torch
+
+    import synth
+    from paper_2011_03602_amd import frontend as fe
+
+    src = open(FRONTEND_PROGRAM).read()
+    t0 = time.perf_counter()
+    prog = fe.analyse(src)
+    t_analyse = time.perf_counter() - t0
+    names = {lib: a for a, lib in prog.binding.items()}
+    I, J, K, iters = 129, 129, 257, 50
+    arrays = synth.make_problem(I, J, K)
+    lups = interior(I, J, K) * iters
+    res = {"program": "tests/programs/relax.py", "analysis_ms": round(t_analyse * 1e3, 2),
+           "grid": f"{I}x{J}x{K}", "iterations": iters}
+    for label, gene in (("whole nests", 0b001_001_001), ("per-plane regions", 0b010_010_010)):
+        for via in ("direct", "frontend"):
+            best = None
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if via == "direct":
+                    g = ofl.Grid(arrays)
+                    ofl.ofl_set_loop_gene(g.handle, gene, ofl.OFL_XFER_HOISTED)
+                    ofl.ofl_jacobi_run(g.handle, iters, OMEGA)
+                    g.close()
+                else:
+                    args = {names[k]: v for k, v in arrays.items()}
+                    args.update({prog.symbols["omega"]: float(OMEGA), "steps": iters})
+                    fe.offload(prog, args, gene)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                best = dt if best is None else min(best, dt)
+            res[f"{label}, {via}: GLUP/s end to end"] = round(lups / best / 1e9, 3)
+            log(f"front end: {label} via {via}: {best:.3f} s")
+    small = synth.make_problem(9, 7, 6)
+    args = {names[k]: np.array(v, dtype=np.float32) for k, v in small.items()}
+    args.update({prog.symbols["omega"]: float(OMEGA), "steps": 2})
+    t0 = time.perf_counter()
+    fe.run_python(src, args)
+    dt = time.perf_counter() - t0
+    res["interpreted program, 9x7x6 x2: GLUP/s"] = round(interior(9, 7, 6) * 2 / dt / 1e9, 8)
+    return res
 
 
 def run_precision(ofl):

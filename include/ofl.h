@@ -264,7 +264,7 @@ int ofl_reset_stats(ofl_grid *g);
 /* ---- the transfer planner as a pure function ------------------------------ */
 typedef struct ofl_xfer {
     int iter;   /* iteration index; -1 before the loop (data_enter), iters after it */
-    int nest;   /* 0 S, 1 R, 2 C; -1 outside the nests */
+    int nest;   /* 0 S, 1 R, 2 C (nest index for ofl_plan_nests); -1 outside the nests */
     int when;   /* 0 before the nest, 1 after it */
     int array;  /* OFL_ARR_* */
     int dir;    /* 0 host->device, 1 device->host */
@@ -279,6 +279,31 @@ typedef struct ofl_xfer {
  * too small. */
 int ofl_plan(unsigned mask, int xfer_mode, int iters, int sync_host_at_end, uint8_t host_valid[14],
              uint8_t dev_valid[14], ofl_xfer *out, int cap, int *count);
+
+/* The planner over any program of loop nests (Sec. 4.2.2: transfers follow from
+ * which side sets and which side references each variable). Each nest is
+ * given by bit sets over array ids 0..narrays-1: the arrays it reads, the
+ * arrays it writes, and the arrays it writes only in part while the rest
+ * stays live (those must be whole on the writer's side first, so they move as
+ * if read). live_after: arrays the CPU program references after the loop. The
+ * gene `mask` has one bit per nest (1 = GPU). Otherwise as ofl_plan, which is
+ * this function on the table ofl_program_vars returns. EINVAL for nnests
+ * outside 1..OFL_MAX_NESTS, narrays outside 1..OFL_MAX_ARRAYS, bits beyond
+ * narrays or nnests, or bad state/output arguments. */
+#define OFL_MAX_NESTS 8
+#define OFL_MAX_ARRAYS 32
+typedef struct ofl_nest_vars {
+    uint32_t reads;    /* bit a: the nest reads array a */
+    uint32_t writes;   /* bit a: the nest writes array a */
+    uint32_t partial;  /* bit a: it writes part of array a, the rest of which stays live */
+} ofl_nest_vars;
+int ofl_plan_nests(const ofl_nest_vars *nests, int nnests, int narrays, uint32_t live_after, unsigned mask,
+                   int xfer_mode, int iters, int sync_host_at_end, uint8_t *host_valid, uint8_t *dev_valid,
+                   ofl_xfer *out, int cap, int *count);
+
+/* The library's program in that form: the nests S, R, C over the OFL_ARR_*
+ * arrays, and the arrays referenced after the loop (p). EINVAL on NULL. */
+int ofl_program_vars(ofl_nest_vars out[3], uint32_t *live_after);
 
 /* ---- many independent grids in one launch sequence ------------------------- */
 typedef struct ofl_batch ofl_batch;

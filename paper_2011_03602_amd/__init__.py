@@ -82,6 +82,13 @@ class OflXfer(ctypes.Structure):
         return (self.iter, self.nest, self.when, self.array, self.dir)
 
 
+class OflNestVars(ctypes.Structure):
+    _fields_ = [("reads", ctypes.c_uint32), ("writes", ctypes.c_uint32), ("partial", ctypes.c_uint32)]
+
+    def as_tuple(self):
+        return (self.reads, self.writes, self.partial)
+
+
 class OflGaParams(ctypes.Structure):
     _fields_ = [("population", ctypes.c_int), ("generations", ctypes.c_int), ("seed", ctypes.c_uint64),
                 ("crossover", ctypes.c_double), ("mutation", ctypes.c_double), ("elite", ctypes.c_int),
@@ -147,6 +154,11 @@ _SIGS = {
     "ofl_plan": ([ctypes.c_uint, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_uint8),
                   ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(OflXfer), ctypes.c_int,
                   ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "ofl_plan_nests": ([ctypes.POINTER(OflNestVars), ctypes.c_int, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint,
+                        ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_uint8),
+                        ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(OflXfer), ctypes.c_int,
+                        ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "ofl_program_vars": ([ctypes.POINTER(OflNestVars), ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
     "ofl_batch_create": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(OflTile),
                           ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "ofl_batch_destroy": ([ctypes.c_void_p], None),
@@ -313,6 +325,38 @@ def ofl_plan(mask: int, xfer_mode: int, iters: int, sync_host_at_end: bool = Tru
     _check(lib().ofl_plan(mask, xfer_mode, iters, 1 if sync_host_at_end else 0, hv, dv, buf, count.value,
                           ctypes.byref(count)))
     return [buf[t].as_tuple() for t in range(count.value)], list(hv), list(dv)
+
+
+def ofl_plan_nests(nests: Sequence[Sequence[int]], narrays: int, live_after: int, mask: int, xfer_mode: int,
+                   iters: int, sync_host_at_end: bool = True, host_valid: Optional[Sequence[int]] = None,
+                   dev_valid: Optional[Sequence[int]] = None):
+    """The planner over any program: nests = [(reads, writes, partial) bit sets], one per nest.
+    Returns (list of (iter, nest, when, array, dir), host_valid, dev_valid)."""
+    nv = (OflNestVars * len(nests))(*[OflNestVars(*n) for n in nests])
+
+    def state():
+        hv = (ctypes.c_uint8 * narrays)(*(host_valid if host_valid is not None else [1] * narrays))
+        dv = (ctypes.c_uint8 * narrays)(*(dev_valid if dev_valid is not None else [0] * narrays))
+        return hv, dv
+
+    hv, dv = state()
+    count = ctypes.c_int()
+    args = (nv, len(nests), narrays, live_after, mask, xfer_mode, iters, 1 if sync_host_at_end else 0)
+    rc = lib().ofl_plan_nests(*args, hv, dv, None, 0, ctypes.byref(count))
+    if rc not in (OFL_OK, OFL_ENOMEM):
+        _check(rc)
+    hv, dv = state()
+    buf = (OflXfer * max(1, count.value))()
+    _check(lib().ofl_plan_nests(*args, hv, dv, buf, count.value, ctypes.byref(count)))
+    return [buf[t].as_tuple() for t in range(count.value)], list(hv), list(dv)
+
+
+def ofl_program_vars():
+    """The library's program as [(reads, writes, partial)] for S, R, C, and the arrays read after the loop."""
+    nv = (OflNestVars * 3)()
+    live = ctypes.c_uint32()
+    _check(lib().ofl_program_vars(nv, ctypes.byref(live)))
+    return [x.as_tuple() for x in nv], live.value
 
 
 def ofl_batch_create(grids: Sequence, tile: Optional[OflTile] = None) -> ctypes.c_void_p:

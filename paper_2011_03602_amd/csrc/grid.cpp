@@ -998,15 +998,43 @@ int ofl_reset_stats(ofl_grid *g) {
 
 int ofl_plan(unsigned mask, int xfer_mode, int iters, int sync_host_at_end, uint8_t host_valid[14],
              uint8_t dev_valid[14], ofl_xfer *out, int cap, int *count) {
+    const Program &prog = jacobi_program();
+    ofl_nest_vars nv[3];
+    for (int n = 0; n < 3; ++n)
+        nv[n] = {prog.nests[n].reads, prog.nests[n].writes, prog.nests[n].partial};
+    return ofl_plan_nests(nv, prog.nnests, prog.narrays, prog.live_after, mask, xfer_mode, iters, sync_host_at_end,
+                          host_valid, dev_valid, out, cap, count);
+}
+
+int ofl_plan_nests(const ofl_nest_vars *nests, int nnests, int narrays, uint32_t live_after, unsigned mask,
+                   int xfer_mode, int iters, int sync_host_at_end, uint8_t *host_valid, uint8_t *dev_valid,
+                   ofl_xfer *out, int cap, int *count) {
     return guarded(nullptr, [&] {
-        if (mask > OFL_MASK_ALL_GPU)
-            fail(OFL_EINVAL, "mask has bits above bit 2");
+        if (!nests || nnests < 1 || nnests > kMaxNests || narrays < 1 || narrays > kMaxArrays)
+            fail(OFL_EINVAL, "nests must hold 1..8 entries over 1..32 arrays");
+        const uint32_t all = narrays == 32 ? 0xffffffffu : ((1u << narrays) - 1u);
+        Program prog{};
+        prog.nnests = nnests;
+        prog.narrays = narrays;
+        prog.live_after = live_after;
+        for (int n = 0; n < nnests; ++n) {
+            const ofl_nest_vars &x = nests[n];
+            if (((x.reads | x.writes | x.partial) & ~all) != 0)
+                fail(OFL_EINVAL, "a nest names an array beyond narrays");
+            if ((x.partial & ~x.writes) != 0)
+                fail(OFL_EINVAL, "a partial write must also be a write");
+            prog.nests[n] = {x.reads, x.writes, x.partial};
+        }
+        if ((live_after & ~all) != 0)
+            fail(OFL_EINVAL, "live_after names an array beyond narrays");
+        if ((mask >> nnests) != 0)
+            fail(OFL_EINVAL, "mask has bits beyond the nests");
         if (xfer_mode != OFL_XFER_PER_ITER && xfer_mode != OFL_XFER_HOISTED)
             fail(OFL_EINVAL, "unknown xfer_mode");
         if (iters < 0 || !host_valid || !dev_valid || !count || cap < 0 || (cap > 0 && !out))
             fail(OFL_EINVAL, "bad iters, state or output arguments");
-        Validity v;
-        for (int a = 0; a < OFL_NARRAYS; ++a) {
+        Validity v = fresh_validity();
+        for (int a = 0; a < narrays; ++a) {
             v.host[a] = host_valid[a] ? 1 : 0;
             v.dev[a] = dev_valid[a] ? 1 : 0;
             if (!v.host[a] && !v.dev[a])
@@ -1014,15 +1042,15 @@ int ofl_plan(unsigned mask, int xfer_mode, int iters, int sync_host_at_end, uint
         }
         std::vector<Xfer> xs;
         for (int it = 0; it < iters; ++it)
-            for (int nest = 0; nest < 3; ++nest) {
+            for (int nest = 0; nest < nnests; ++nest) {
                 const bool gpu = ((mask >> nest) & 1u) != 0;
-                plan_before(it, nest, gpu, xfer_mode, v, xs);
-                plan_after(it, nest, gpu, xfer_mode, v, xs);
+                plan_before(prog, it, nest, gpu, xfer_mode, v, xs);
+                plan_after(prog, it, nest, gpu, xfer_mode, v, xs);
             }
         if (sync_host_at_end && iters > 0)
-            plan_sync_host(iters, v, xs);
+            plan_sync_host(prog, iters, v, xs);
         *count = static_cast<int>(xs.size());
-        for (int a = 0; a < OFL_NARRAYS; ++a) {
+        for (int a = 0; a < narrays; ++a) {
             host_valid[a] = v.host[a];
             dev_valid[a] = v.dev[a];
         }
@@ -1031,6 +1059,17 @@ int ofl_plan(unsigned mask, int xfer_mode, int iters, int sync_host_at_end, uint
             out[t] = ofl_xfer{xs[t].iter, xs[t].nest, xs[t].when, xs[t].array, xs[t].dir};
         if (static_cast<int>(xs.size()) > cap)
             fail(OFL_ENOMEM, "out has fewer entries than the plan");
+    });
+}
+
+int ofl_program_vars(ofl_nest_vars out[3], uint32_t *live_after) {
+    return guarded(nullptr, [&] {
+        if (!out || !live_after)
+            fail(OFL_EINVAL, "NULL argument");
+        const Program &prog = jacobi_program();
+        for (int n = 0; n < 3; ++n)
+            out[n] = {prog.nests[n].reads, prog.nests[n].writes, prog.nests[n].partial};
+        *live_after = prog.live_after;
     });
 }
 

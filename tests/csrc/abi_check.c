@@ -194,6 +194,39 @@ int main(void) {
         CHECK(ofl_plan(7, 1, 1, 1, hv, dv, NULL, 0, &count) == OFL_EINVAL);
     }
 
+    /* the planner over a caller's program table equals ofl_plan on the library's own */
+    {
+        ofl_nest_vars nv[3];
+        uint32_t live = 0;
+        CHECK(ofl_program_vars(nv, &live) == OFL_OK && live == (1u << OFL_ARR_P));
+        for (unsigned mask = 0; mask < 8; ++mask)
+            for (int mode = 0; mode < 2; ++mode) {
+                ofl_xfer a[256], b[256];
+                uint8_t h1[14], d1[14], h2[32], d2[32];
+                memset(h1, 1, sizeof h1);
+                memset(d1, 0, sizeof d1);
+                memset(h2, 1, sizeof h2);
+                memset(d2, 0, sizeof d2);
+                int ca = -1, cb = -2;
+                CHECK(ofl_plan(mask, mode, 4, 1, h1, d1, a, 256, &ca) == OFL_OK);
+                CHECK(ofl_plan_nests(nv, 3, 14, live, mask, mode, 4, 1, h2, d2, b, 256, &cb) == OFL_OK);
+                CHECK(ca == cb && memcmp(a, b, sizeof(ofl_xfer) * (size_t)ca) == 0);
+                CHECK(memcmp(h1, h2, 14) == 0 && memcmp(d1, d2, 14) == 0);
+            }
+        uint8_t h[32], d[32];
+        int c;
+        memset(h, 1, sizeof h);
+        memset(d, 0, sizeof d);
+        CHECK(ofl_plan_nests(nv, 0, 14, live, 0u, 1, 1, 1, h, d, NULL, 0, &c) == OFL_EINVAL);
+        CHECK(ofl_plan_nests(nv, 3, 33, live, 0u, 1, 1, 1, h, d, NULL, 0, &c) == OFL_EINVAL);
+        CHECK(ofl_plan_nests(nv, 3, 12, live, 0u, 1, 1, 1, h, d, NULL, 0, &c) == OFL_EINVAL);
+        CHECK(ofl_plan_nests(nv, 3, 14, live, 8u, 1, 1, 1, h, d, NULL, 0, &c) == OFL_EINVAL);
+        ofl_nest_vars bad = {1u, 0u, 2u};
+        CHECK(ofl_plan_nests(&bad, 1, 4, 0u, 1u, 1, 1, 1, h, d, NULL, 0, &c) == OFL_EINVAL);
+        ofl_nest_vars wide = {0xffffffffu, 1u, 0u};
+        CHECK(ofl_plan_nests(&wide, 1, 32, 1u, 1u, 0, 2, 1, h, d, NULL, 0, &c) == OFL_ENOMEM && c == 66);
+    }
+
     /* the loop table, every loop gene, region settings */
     {
         problem q;
