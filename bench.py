@@ -269,8 +269,10 @@ FRONTEND_PROGRAM = os.path.join(ROOT, "tests", "programs", "relax.py")
 
 def run_frontend(ofl):
     """The same Jacobi program written in Python with its own names, read by the
-    front end and offloaded through the library: analysis time, end-to-end runs
-    against the direct interface, and the interpreted program's own rate."""
+    front end and offloaded through the library: analysis time, the run
+    (ofl_jacobi_run, transfers included) against the same gene set through the
+    interface directly, the front end's setup and write-back, and the
+    interpreted program's own rate."""
     import torch
 
     import synth
@@ -281,38 +283,43 @@ def run_frontend(ofl):
     prog = fe.analyse(src)
     t_analyse = time.perf_counter() - t0
     names = {lib: a for a, lib in prog.binding.items()}
-    I, J, K, iters = 129, 129, 257, 50
+    I, J, K, iters = 129, 129, 257, 200
     arrays = synth.make_problem(I, J, K)
     lups = interior(I, J, K) * iters
     res = {"program": "tests/programs/relax.py", "analysis_ms": round(t_analyse * 1e3, 2),
-           "grid": f"{I}x{J}x{K}", "iterations": iters}
+           "grid": f"{I}x{J}x{K}", "iterations": iters, "rows": []}
     for label, gene in (("whole nests", 0b001_001_001), ("per-plane regions", 0b010_010_010)):
         for via in ("direct", "frontend"):
-            best = None
+            runs = []
             for _ in range(3):
                 torch.cuda.synchronize()
-                t0 = time.perf_counter()
                 if via == "direct":
+                    t0 = time.perf_counter()
                     g = ofl.Grid(arrays)
                     ofl.ofl_set_loop_gene(g.handle, gene, ofl.OFL_XFER_HOISTED)
+                    t1 = time.perf_counter()
                     ofl.ofl_jacobi_run(g.handle, iters, OMEGA)
+                    t2 = time.perf_counter()
                     g.close()
+                    tm = {"setup": t1 - t0, "run": t2 - t1, "writeback": 0.0}
                 else:
                     args = {names[k]: v for k, v in arrays.items()}
                     args.update({prog.symbols["omega"]: float(OMEGA), "steps": iters})
-                    fe.offload(prog, args, gene)
-                torch.cuda.synchronize()
-                dt = time.perf_counter() - t0
-                best = dt if best is None else min(best, dt)
-            res[f"{label}, {via}: GLUP/s end to end"] = round(lups / best / 1e9, 3)
-            log(f"front end: {label} via {via}: {best:.3f} s")
+                    tm = {}
+                    fe.offload(prog, args, gene, timings=tm)
+                runs.append(tm)
+            best = min(runs, key=lambda t: t["run"])
+            res["rows"].append({"gene": label, "via": via, "run_glups": round(lups / best["run"] / 1e9, 3),
+                                "run_ms": round(best["run"] * 1e3, 2), "setup_ms": round(best["setup"] * 1e3, 2),
+                                "writeback_ms": round(best["writeback"] * 1e3, 2)})
+            log(f"front end: {label} via {via}: run {best['run'] * 1e3:.1f} ms")
     small = synth.make_problem(9, 7, 6)
     args = {names[k]: np.array(v, dtype=np.float32) for k, v in small.items()}
     args.update({prog.symbols["omega"]: float(OMEGA), "steps": 2})
     t0 = time.perf_counter()
     fe.run_python(src, args)
     dt = time.perf_counter() - t0
-    res["interpreted program, 9x7x6 x2: GLUP/s"] = round(interior(9, 7, 6) * 2 / dt / 1e9, 8)
+    res["interpreted_program_9x7x6_x2_glups"] = round(interior(9, 7, 6) * 2 / dt / 1e9, 8)
     return res
 
 

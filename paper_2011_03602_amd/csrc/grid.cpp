@@ -227,8 +227,11 @@ void prof_begin(ofl_grid *g, int nest) {
         return;
     if (g->ev.size() < 2 * (g->ev_used + 1)) {
         for (int t = 0; t < 2; ++t) {
+            // Timing only (read after a stream synchronisation): no system-scope
+            // fence, which would write back and invalidate the caches between
+            // nests and slow the work being timed.
             hipEvent_t e;
-            hip_check(hipEventCreate(&e), "hipEventCreate");
+            hip_check(hipEventCreateWithFlags(&e, hipEventDisableSystemFence), "hipEventCreateWithFlags");
             g->ev.push_back(e);
         }
         g->ev_nest.push_back(0);

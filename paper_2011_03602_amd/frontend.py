@@ -35,6 +35,7 @@ ofl_grid_search_loops.
 from __future__ import annotations
 
 import ast
+import time
 from dataclasses import dataclass, field
 from fractions import Fraction
 from typing import Dict, List, Optional, Tuple
@@ -738,18 +739,25 @@ def _finish(prog: Program, args, g: Grid, gosa: float):
 
 
 def offload(prog: Program, args: Dict[str, object], gene: int, xfer_mode: int = OFL_XFER_HOISTED,
-            stats: Optional[list] = None, **grid_kw):
+            stats: Optional[list] = None, timings: Optional[dict] = None, **grid_kw):
     """Run the program with the loop gene (bit b: the b-th loop that passes the
     screen, in program order) through the library. Arrays the program
     references after the loop are written back in place; returns what the
-    program returns."""
+    program returns. timings, if given, receives the seconds spent setting up
+    the grid, in ofl_jacobi_run (transfers included) and writing back."""
+    t0 = time.perf_counter()
     g, iters, omega = _grid(prog, args, **grid_kw)
     try:
         ofl_set_loop_gene(g.handle, gene, xfer_mode)
+        t1 = time.perf_counter()
         gosa = ofl_jacobi_run(g.handle, iters, omega)
+        t2 = time.perf_counter()
         if stats is not None:
             stats.append(ofl_get_stats(g.handle))
-        return _finish(prog, args, g, gosa)
+        out = _finish(prog, args, g, gosa)
+        if timings is not None:
+            timings.update(setup=t1 - t0, run=t2 - t1, writeback=time.perf_counter() - t2)
+        return out
     finally:
         g.close()
 
