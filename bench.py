@@ -13,7 +13,7 @@ host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-variants]
        [--skip-cpu-baseline] [--profile-only NAME]
-       [--config headline|masks|precision|loops]
+       [--config headline|masks|precision|loops|blocks]
 """
 
 from __future__ import annotations
@@ -323,6 +323,65 @@ def run_frontend(ofl):
     return res
 
 
+PEAK_FP32_MFMA_TFLOPS = 157.3
+GEMM_SHAPES = ((4096, 4096, 4096), (8192, 8192, 8192), (8192, 4096, 1024))
+
+
+def time_gemm(ofl, M, N, K, reps=10):
+    """Average duration of ofl_gemm_f32 launches (HIP events on the launch stream)."""
+    import torch
+
+    g = torch.Generator(device="cuda").manual_seed(M + N + K)
+    a = torch.rand((M, K), device="cuda", generator=g)
+    b = torch.rand((K, N), device="cuda", generator=g)
+    c = torch.empty((M, N), device="cuda")
+    s = torch.cuda.current_stream()
+    for _ in range(2):
+        ofl.ofl_gemm_f32(M, N, K, a.data_ptr(), K, b.data_ptr(), N, c.data_ptr(), N, s.cuda_stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        ofl.ofl_gemm_f32(M, N, K, a.data_ptr(), K, b.data_ptr(), N, c.data_ptr(), N, s.cuda_stream)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e-3
+
+
+def run_blocks(ofl):
+    """Function-block offload: the matrix-product routine against the FP32
+    matrix-core peak, and the block trials of a Python program with three
+    matrix products (each block alone, then the faster ones combined)."""
+    from paper_2011_03602_amd import blocks as fb
+
+    out = {"config": "function blocks: FP32 matrix product on the matrix cores; block trials", "gemm": []}
+    for M, N, K in GEMM_SHAPES:
+        sec = time_gemm(ofl, M, N, K)
+        tflops = 2.0 * M * N * K / sec / 1e12
+        out["gemm"].append({"M": M, "N": N, "K": K, "us": round(sec * 1e6, 1), "tflops": round(tflops, 2),
+                            "frac_of_fp32_mfma_peak": round(tflops / PEAK_FP32_MFMA_TFLOPS, 4)})
+        log(f"gemm {M}x{N}x{K}: {tflops:.1f} TFLOP/s")
+    src = open(os.path.join(ROOT, "tests", "programs", "mlp.py")).read()
+    prog = fb.analyse_blocks(src)
+    rng = np.random.default_rng(0)
+    n, d = 8192, 4096
+    args = {"x": rng.uniform(-1, 1, (n, d)).astype(np.float32),
+            "w1": (rng.uniform(-1, 1, (d, d)) / np.sqrt(d)).astype(np.float32),
+            "w2": (rng.uniform(-1, 1, (d, d)) / np.sqrt(d)).astype(np.float32),
+            "w3": (rng.uniform(-1, 1, (d, 16)) / np.sqrt(d)).astype(np.float32)}
+    t0 = time.perf_counter()
+    res = fb.trial_blocks(prog, args, repeats=3)
+    out["trials"] = {"program": "tests/programs/mlp.py", "shapes": "x 8192x4096, w1 w2 4096x4096, w3 4096x16",
+                     "blocks": [f"{b.name} (line {b.line})" for b in prog.blocks],
+                     "patterns": [{"gene": format(t.gene, f"0{len(prog.blocks)}b"), "seconds": t.seconds,
+                                   "status": t.status, "max_rel_err": t.max_rel_err} for t in res["trials"]],
+                     "faster_alone": res["faster_alone"], "best_gene": format(res["best"].gene, f"0{len(prog.blocks)}b"),
+                     "search_seconds": round(time.perf_counter() - t0, 2)}
+    base = next(t for t in res["trials"] if t.gene == 0).seconds
+    out["trials"]["speedup_vs_host"] = round(base / res["best"].seconds, 2)
+    log(f"block trials: best {out['trials']['best_gene']}, {out['trials']['speedup_vs_host']}x the host program")
+    return out
+
+
 def run_precision(ofl):
     """Errors of every storage format and residual mode against the FP64
     oracle on the FP32 inputs, 257x257x513, 100 iterations."""
@@ -384,13 +443,14 @@ def main():
     ap.add_argument("--tune-batch", action="store_true", help="run the GA tile search before the batched run")
     ap.add_argument("--oracle-iters", type=int, default=10)
     ap.add_argument("--profile-only", default=None,
-                    help="headline|bf16|batch|copy: run just that under a profiler, print no JSON")
+                    help="headline|bf16|batch|copy|gemm: run just that under a profiler, print no JSON")
     ap.add_argument("--profile-iters", type=int, default=ITERS,
                     help="iterations per step in --profile-only runs (counter passes use a few)")
-    ap.add_argument("--config", default="headline", choices=["headline", "masks", "precision", "loops"],
+    ap.add_argument("--config", default="headline", choices=["headline", "masks", "precision", "loops", "blocks"],
                     help="headline: the benchmark line; masks: every gene x placement at 129x129x257; "
                          "precision: format/residual errors vs the FP64 oracle at 257x257x513; "
-                         "loops: per-loop genes (region levels) and their GA search")
+                         "loops: per-loop genes (region levels) and their GA search; "
+                         "blocks: the matrix-product routine and function-block trials")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -415,6 +475,14 @@ def main():
         return
     if args.config == "loops":
         print(json.dumps(run_loops(ofl)), flush=True)
+        return
+    if args.config == "blocks":
+        print(json.dumps(run_blocks(ofl)), flush=True)
+        return
+    if args.profile_only == "gemm":
+        for M, N, K in GEMM_SHAPES:
+            time_gemm(ofl, M, N, K, reps=max(1, args.steps))
+        log("profile run done")
         return
     if args.profile_only == "copy":
         # Copy kernel of known size: calibrates the HBM byte counters.

@@ -427,6 +427,23 @@ typedef struct ofl_loop_search_result {
 int ofl_grid_search_loops(ofl_grid *g, const ofl_ga_params *ga, int iters, float omega, int xfer_mode,
                           double time_limit_ms, ofl_loop_search_result *out);
 
+/* ---- function-block offload (Sec. 3.2.2, Sec. 4.2.1) ----------------------
+ * GPU routines that a recognised host function block (a call of a known
+ * library routine) is replaced with; the Python front end's pattern table
+ * maps numpy's matrix products onto ofl_gemm_f32. */
+
+/* Matrix product C = A B of row-major FP32 matrices in device memory: A is
+ * M x K with row stride lda >= K, B is K x N with ldb >= N, C is M x N with
+ * ldc >= N (strides in elements). C must not overlap A or B. The library's
+ * matrix-core kernel (FP32 products, FP32 accumulation) is queued on stream (a
+ * hipStream_t; NULL: the default stream) and the call returns without
+ * waiting. Nothing is read or written when M or N is 0; K = 0 sets C to 0.
+ * EINVAL for negative sizes, M above 65535 * 128, short strides, or a NULL
+ * pointer to an operand the product reads or writes; EDEVICE when the launch
+ * fails. */
+int ofl_gemm_f32(int M, int N, int K, const float *A, int lda, const float *B, int ldb, float *C, int ldc,
+                 void *stream);
+
 /* ---- measurement helper ---------------------------------------------------- */
 /* Device-to-device copy of bytes (multiple of 16, 16-byte aligned pointers)
  * with the library's streaming copy kernel on the given stream (NULL = the

@@ -1,4 +1,5 @@
-"""FP64 CPU oracle of the offloaded Jacobi program (ctypes front of oracle.c).
+"""FP64 CPU oracle of the offloaded Jacobi program and of the matrix-product
+function block (ctypes front of oracle.c).
 
 TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
 CPU-baseline leg use this package; the product library never does. It shares
@@ -43,6 +44,8 @@ def _load():
         lib.oracle_bf16_rne.restype = ctypes.c_float
         lib.oracle_bf16_rne_array.argtypes = [_FP, _FP, ctypes.c_size_t]
         lib.oracle_bf16_rne_array.restype = None
+        lib.oracle_gemm.argtypes = [ctypes.c_int] * 3 + [_DP, ctypes.c_int, _DP, ctypes.c_int, _DP, ctypes.c_int]
+        lib.oracle_gemm.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -140,3 +143,17 @@ def offset_bias(x):
     lo = float(x.min())
     hi = float(x.max())
     return np.float32(0.5 * (lo + hi))
+
+
+def gemm(a, b):
+    """C = A B in FP64 of the given operands (widened), by oracle_gemm."""
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    b = np.ascontiguousarray(np.asarray(b, dtype=np.float64))
+    if a.ndim != 2 or b.ndim != 2 or a.shape[1] != b.shape[0]:
+        raise ValueError("gemm needs an M x K and a K x N matrix")
+    M, K = a.shape
+    N = b.shape[1]
+    c = np.zeros((M, N), dtype=np.float64)
+    _check(_load().oracle_gemm(M, N, K, _ptr(a), max(K, 1), _ptr(b), max(N, 1), _ptr(c), max(N, 1)),
+           "oracle_gemm")
+    return c

@@ -13,14 +13,16 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose: bool = False) -> str:
+    tmp = LIB + ".tmp"
     cmd = [
         "gcc", "-O2", "-std=c99", "-fPIC", "-shared",
         "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
-        "-o", LIB, os.path.join(HERE, "oracle.c"), "-lm",
+        "-o", tmp, os.path.join(HERE, "oracle.c"), "-lm",
     ]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)  # a reader never sees a half-written library
     return LIB
 
 

@@ -172,3 +172,22 @@ void oracle_bf16_rne_array(const float *in, float *out, size_t n)
     for (size_t t = 0; t < n; ++t)
         out[t] = oracle_bf16_rne(in[t]);
 }
+
+/*
+ * Matrix product, the definition written out: each element of C is the sum
+ * over k of the products along row i of A and column j of B, accumulated in
+ * FP64 in increasing k.
+ */
+int oracle_gemm(int M, int N, int K, const double *a, int lda, const double *b, int ldb, double *c, int ldc)
+{
+    if (M < 0 || N < 0 || K < 0 || lda < K || ldb < N || ldc < N)
+        return -1;
+    for (int i = 0; i < M; ++i)
+        for (int j = 0; j < N; ++j) {
+            double sum = 0.0;
+            for (int k = 0; k < K; ++k)
+                sum += a[(size_t)i * lda + k] * b[(size_t)k * ldb + j];
+            c[(size_t)i * ldc + j] = sum;
+        }
+    return 0;
+}

@@ -36,6 +36,12 @@ int oracle_jacobi(int I, int J, int K, const double *const co[ORACLE_NCOEF], dou
 float oracle_bf16_rne(float x);
 void oracle_bf16_rne_array(const float *in, float *out, size_t n);
 
+/* Matrix product C = A B in FP64 (row-major; lda, ldb, ldc are row strides in
+ * elements): c[i][j] = sum over k of a[i][k] * b[k][j], summed in k order.
+ * The plain definition of the matrix-product function block. Returns 0, or -1
+ * for negative sizes or strides shorter than the rows. */
+int oracle_gemm(int M, int N, int K, const double *a, int lda, const double *b, int ldb, double *c, int ldc);
+
 #ifdef __cplusplus
 }
 #endif

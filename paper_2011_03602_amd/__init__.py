@@ -174,6 +174,8 @@ _SIGS = {
                                  ctypes.POINTER(OflOffloadResult)], ctypes.c_int),
     "ofl_grid_search_loops": ([ctypes.c_void_p, ctypes.POINTER(OflGaParams), ctypes.c_int, ctypes.c_float,
                                ctypes.c_int, ctypes.c_double, ctypes.POINTER(OflLoopSearchResult)], ctypes.c_int),
+    "ofl_gemm_f32": ([ctypes.c_int] * 3 + [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                           ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "ofl_device_copy": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
     "ofl_last_error": ([], ctypes.c_char_p),
     "ofl_version": ([], ctypes.c_char_p),
@@ -430,6 +432,12 @@ def ofl_grid_search_offload(g, iters: int, omega: float, ga: Optional[OflGaParam
     _check(lib().ofl_grid_search_offload(g, ctypes.byref(ga) if ga is not None else None, iters, omega,
                                          ctypes.byref(r)))
     return r
+
+
+def ofl_gemm_f32(M: int, N: int, K: int, a_ptr: int, lda: int, b_ptr: int, ldb: int, c_ptr: int, ldc: int,
+                 stream: Optional[int] = None) -> None:
+    """C = A B on device pointers (row-major FP32, strides in elements), queued on stream."""
+    _check(lib().ofl_gemm_f32(M, N, K, a_ptr, lda, b_ptr, ldb, c_ptr, ldc, stream))
 
 
 def ofl_device_copy(dst_ptr: int, src_ptr: int, nbytes: int, stream: Optional[int] = None) -> None:

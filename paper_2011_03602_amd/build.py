@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build", "ofl")
 LIB = os.path.join(HERE, "libofl.so")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "grid.cpp", "cpu_nests.cpp", "batch.cpp", "tune.cpp"]
+SOURCES = ["kernels.hip", "gemm.hip", "grid.cpp", "cpu_nests.cpp", "batch.cpp", "tune.cpp", "blocks.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

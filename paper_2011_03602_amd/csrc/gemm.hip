@@ -1,0 +1,157 @@
+// FP32 matrix product on the matrix cores: the GPU routine a recognised host
+// matrix-product block is replaced with (function-block offload, Sec. 3.2.2,
+// Sec. 4.2.1).
+//
+// C = A B for row-major FP32 matrices. A work-group of four waves owns a
+// 128 x 128 tile of C. Each wave owns a 64 x 64 quarter as 2 x 2 accumulator
+// tiles of 32 x 32, updated by v_mfma_f32_32x32x2_f32 (FP32 operands, FP32
+// accumulation). The K dimension advances in stages of 16: the next stage's
+// A and B tiles are fetched from global memory into registers while the
+// current stage, held in LDS, feeds the matrix cores. LDS is double-buffered,
+// so one barrier per stage suffices.
+//
+// Operand layout of the 32x32x2 instruction (wave64): lane l supplies
+// A[l % 32][l / 32] and B[l / 32][l % 32]; accumulator register r of lane l
+// holds C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "ofl_internal.hpp"
+
+namespace ofl {
+
+namespace {
+
+constexpr int kTileM = 128, kTileN = 128, kTileK = 16;
+constexpr int kGemmThreads = 256;
+constexpr int kLdsPad = 4;  // floats of padding per LDS row
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+struct GemmArgs {
+    int M, N, K;
+    const float *A;
+    int lda;
+    const float *B;
+    int ldb;
+    float *C;
+    int ldc;
+};
+
+// Fetch this thread's share of the A (128 x 16) and B (16 x 128) tiles at k0
+// into registers: A row tid / 2, columns (tid % 2) * 8 .. +8; B row tid / 16,
+// columns (tid % 16) * 8 .. +8. Out-of-range elements read as zero. `vec`:
+// the block's tiles lie inside the matrices and every row start is 16-byte
+// aligned, so whole float4 loads are used.
+__device__ __forceinline__ void fetch(const GemmArgs &g, int m0, int n0, int k0, bool vec, float *ra, float *rb) {
+    const int tid = threadIdx.x;
+    const int am = m0 + (tid >> 1), ak = k0 + (tid & 1) * 8;
+    const int bk = k0 + (tid >> 4), bn = n0 + (tid & 15) * 8;
+    if (vec && k0 + kTileK <= g.K) {
+        const float4 *pa = reinterpret_cast<const float4 *>(g.A + static_cast<size_t>(am) * g.lda + ak);
+        const float4 *pb = reinterpret_cast<const float4 *>(g.B + static_cast<size_t>(bk) * g.ldb + bn);
+        const float4 a0 = pa[0], a1 = pa[1], b0 = pb[0], b1 = pb[1];
+        ra[0] = a0.x; ra[1] = a0.y; ra[2] = a0.z; ra[3] = a0.w;
+        ra[4] = a1.x; ra[5] = a1.y; ra[6] = a1.z; ra[7] = a1.w;
+        rb[0] = b0.x; rb[1] = b0.y; rb[2] = b0.z; rb[3] = b0.w;
+        rb[4] = b1.x; rb[5] = b1.y; rb[6] = b1.z; rb[7] = b1.w;
+        return;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int k = ak + e;
+        ra[e] = (am < g.M && k < g.K) ? g.A[static_cast<size_t>(am) * g.lda + k] : 0.f;
+        const int n = bn + e;
+        rb[e] = (bk < g.K && n < g.N) ? g.B[static_cast<size_t>(bk) * g.ldb + n] : 0.f;
+    }
+}
+
+__global__ __launch_bounds__(kGemmThreads) void gemm_f32_kernel(GemmArgs g, int vec_ok) {
+    // A is kept transposed (k-major) so that a wave's operand fetch for one k
+    // reads 32 consecutive floats.
+    __shared__ float As[2][kTileK][kTileM + kLdsPad];
+    __shared__ float Bs[2][kTileK][kTileN + kLdsPad];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int m0 = blockIdx.y * kTileM, n0 = blockIdx.x * kTileN;
+    const bool vec = vec_ok && m0 + kTileM <= g.M && n0 + kTileN <= g.N;
+
+    floatx16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                acc[i][j][r] = 0.f;
+
+    float ra[8], rb[8];
+    auto stash = [&](int buf) {
+        const int am = tid >> 1, ak = (tid & 1) * 8;
+        const int bk = tid >> 4, bn = (tid & 15) * 8;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            As[buf][ak + e][am] = ra[e];
+            Bs[buf][bk][bn + e] = rb[e];
+        }
+    };
+
+    fetch(g, m0, n0, 0, vec, ra, rb);
+    stash(0);
+    __syncthreads();
+    const int lrow = lane >> 5, lcol = lane & 31;
+    int buf = 0;
+    for (int k0 = 0; k0 < g.K; k0 += kTileK) {
+        const bool more = k0 + kTileK < g.K;
+        if (more)
+            fetch(g, m0, n0, k0 + kTileK, vec, ra, rb);
+#pragma unroll
+        for (int kk = 0; kk < kTileK; kk += 2) {
+            float a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                a[i] = As[buf][kk + lrow][wm + i * 32 + lcol];
+                b[i] = Bs[buf][kk + lrow][wn + i * 32 + lcol];
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        if (more)
+            stash(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = n0 + wn + j * 32 + lcol;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * lrow + (r & 3);
+                if (row < g.M && col < g.N)
+                    g.C[static_cast<size_t>(row) * g.ldc + col] = acc[i][j][r];
+            }
+        }
+}
+
+}  // namespace
+
+void launch_gemm_f32(int M, int N, int K, const float *A, int lda, const float *B, int ldb, float *C, int ldc,
+                     hipStream_t s) {
+    const GemmArgs g{M, N, K, A, lda, B, ldb, C, ldc};
+    const bool aligned = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (reinterpret_cast<uintptr_t>(B) % 16 == 0) &&
+                         lda % 4 == 0 && ldb % 4 == 0;
+    const dim3 grid((N + kTileN - 1) / kTileN, (M + kTileM - 1) / kTileM);
+    hipLaunchKernelGGL(gemm_f32_kernel, grid, dim3(kGemmThreads), 0, s, g, aligned ? 1 : 0);
+    hip_check(hipGetLastError(), "gemm kernel launch");
+}
+
+}  // namespace ofl

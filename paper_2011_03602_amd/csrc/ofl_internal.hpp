@@ -122,6 +122,10 @@ void launch_batch_finalize(const GridView *views, const int *partial_range, int 
 void launch_batch_copyback(const GridView *views, const RowItem *items, int nitems, int vec, int flags,
                            int grid_blocks, hipStream_t s);
 
+// Matrix product on the matrix cores (gemm.hip).
+void launch_gemm_f32(int M, int N, int K, const float *A, int lda, const float *B, int ldb, float *C, int ldc,
+                     hipStream_t s);
+
 int device_cu_count(int device);
 
 }  // namespace ofl

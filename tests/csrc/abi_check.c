@@ -263,6 +263,16 @@ int main(void) {
         drop(&q);
     }
 
+    /* matrix product: argument checks and empty products need no device */
+    CHECK(ofl_gemm_f32(-1, 1, 1, NULL, 1, NULL, 1, NULL, 1, NULL) == OFL_EINVAL);
+    CHECK(ofl_gemm_f32(2, 2, 2, NULL, 1, NULL, 2, NULL, 2, NULL) == OFL_EINVAL);
+    CHECK(ofl_gemm_f32(2, 2, 2, NULL, 2, NULL, 2, NULL, 2, NULL) == OFL_EINVAL);
+    CHECK(ofl_gemm_f32(0, 4, 3, NULL, 3, NULL, 4, NULL, 4, NULL) == OFL_OK);
+    {
+        float dummy[4];
+        CHECK(ofl_gemm_f32(1, 1, 1, dummy, 1, dummy, 1, dummy + 2, 1, NULL) == OFL_EDEVICE);
+    }
+
     /* the GA on a synthetic landscape */
     uint32_t target = 0x5au;
     ofl_ga_params ga = {16, 15, 7ull, 0.9, 0.08, 1, 1, 1, 1e-5};

@@ -28,6 +28,9 @@ void launch_batch_finalize_parts(const GridView *, const double *, const long lo
 void launch_batch_residual(const GridView *, const RowItem *, int, int, int, int, int, hipStream_t) { no_device(); }
 void launch_batch_finalize(const GridView *, const int *, int, float, hipStream_t) { no_device(); }
 void launch_batch_copyback(const GridView *, const RowItem *, int, int, int, int, hipStream_t) { no_device(); }
+void launch_gemm_f32(int, int, int, const float *, int, const float *, int, float *, int, hipStream_t) {
+    no_device();
+}
 int device_cu_count(int) { no_device(); }
 
 }  // namespace ofl

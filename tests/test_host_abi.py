@@ -237,3 +237,14 @@ def test_split_cpu_runs_equal_one_run():
     ofl.ofl_jacobi_run(g2.handle, 3, OMEGA)
     r2 = ofl.ofl_jacobi_run(g2.handle, 3, OMEGA)
     assert np.array_equal(g1.p, g2.p) and r1 == r2
+
+
+def test_gemm_argument_checks_need_no_gpu():
+    for args in ((-1, 1, 1, 0, 1, 0, 1, 0, 1), (2, 2, 2, 0, 1, 0, 2, 0, 2), (2, 2, 2, 0, 2, 0, 1, 0, 2),
+                 (2, 2, 2, 0, 2, 0, 2, 0, 1), (2, 2, 2, 0, 2, 0, 2, 0, 2), (2, 2, 0, 0, 0, 0, 2, 0, 2),
+                 (65535 * 128 + 1, 1, 1, 8, 1, 8, 1, 8, 1)):
+        with pytest.raises(ofl.OflError) as e:
+            ofl.ofl_gemm_f32(*args, None)
+        assert e.value.code == ofl.OFL_EINVAL, args
+    ofl.ofl_gemm_f32(0, 4, 3, 0, 3, 0, 4, 0, 4, None)  # empty result: nothing read or written
+    ofl.ofl_gemm_f32(5, 0, 3, 0, 3, 0, 0, 0, 0, None)

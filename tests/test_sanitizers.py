@@ -14,7 +14,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2011_03602_amd", "csrc")
-HOST_SOURCES = ["grid.cpp", "cpu_nests.cpp", "batch.cpp", "tune.cpp"]
+HOST_SOURCES = ["grid.cpp", "cpu_nests.cpp", "batch.cpp", "tune.cpp", "blocks.cpp"]
 ROCM = "/opt/rocm"
 
 
