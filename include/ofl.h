@@ -258,6 +258,12 @@ typedef struct ofl_stats {
 /* Profiling on: each GPU nest is bracketed by HIP events on the grid's stream
  * and its time is added to kernel_ms at the next synchronisation. */
 int ofl_set_profiling(ofl_grid *g, int on);
+
+/* Which nests profiling brackets (bit n: nest n, as in the offload mask;
+ * default all three). Each bracket adds two event records between kernels,
+ * so timing only the nest of interest disturbs the rest least. EINVAL for
+ * bits above 2. */
+int ofl_set_profiled_nests(ofl_grid *g, unsigned nests);
 int ofl_get_stats(const ofl_grid *g, ofl_stats *out);
 int ofl_reset_stats(ofl_grid *g);
 

@@ -149,6 +149,7 @@ _SIGS = {
     "ofl_set_tile": ([ctypes.c_void_p, ctypes.POINTER(OflTile)], ctypes.c_int),
     "ofl_get_tile": ([ctypes.c_void_p, ctypes.POINTER(OflTile)], ctypes.c_int),
     "ofl_set_profiling": ([ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
+    "ofl_set_profiled_nests": ([ctypes.c_void_p, ctypes.c_uint], ctypes.c_int),
     "ofl_get_stats": ([ctypes.c_void_p, ctypes.POINTER(OflStats)], ctypes.c_int),
     "ofl_reset_stats": ([ctypes.c_void_p], ctypes.c_int),
     "ofl_plan": ([ctypes.c_uint, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_uint8),
@@ -300,6 +301,10 @@ def ofl_get_tile(g) -> OflTile:
 
 def ofl_set_profiling(g, on: bool) -> None:
     _check(lib().ofl_set_profiling(g, 1 if on else 0))
+
+
+def ofl_set_profiled_nests(g, nests: int) -> None:
+    _check(lib().ofl_set_profiled_nests(g, nests))
 
 
 def ofl_get_stats(g) -> OflStats:

@@ -223,7 +223,8 @@ void harvest_events(ofl_grid *g) {
 }
 
 void prof_begin(ofl_grid *g, int nest) {
-    if (!g->profiling)
+    g->prof_open = g->profiling && ((g->prof_nests >> nest) & 1u);
+    if (!g->prof_open)
         return;
     if (g->ev.size() < 2 * (g->ev_used + 1)) {
         for (int t = 0; t < 2; ++t) {
@@ -241,10 +242,11 @@ void prof_begin(ofl_grid *g, int nest) {
 }
 
 void prof_end(ofl_grid *g) {
-    if (!g->profiling)
+    if (!g->prof_open)
         return;
     hip_check(hipEventRecord(g->ev[2 * g->ev_used + 1], g->stream), "hipEventRecord");
     g->ev_used += 1;
+    g->prof_open = false;
 }
 
 void gpu_nest(ofl_grid *g, int nest, float omega) {
@@ -980,6 +982,16 @@ int ofl_set_profiling(ofl_grid *g, int on) {
         if (g->dev_ready)
             grid_sync(g);
         g->profiling = on != 0;
+    });
+}
+
+int ofl_set_profiled_nests(ofl_grid *g, unsigned nests) {
+    return grid_call(g, [&] {
+        if (nests > OFL_MASK_ALL_GPU)
+            fail(OFL_EINVAL, "nests has bits above bit 2");
+        if (g->dev_ready)
+            grid_sync(g);
+        g->prof_nests = nests;
     });
 }
 

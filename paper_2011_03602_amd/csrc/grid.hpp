@@ -50,6 +50,8 @@ struct ofl_grid {
 
     ofl_stats stats{};
     bool profiling = false;
+    unsigned prof_nests = OFL_MASK_ALL_GPU;  // nests whose GPU runs are bracketed by events
+    bool prof_open = false;                  // the current nest recorded its start event
     std::vector<hipEvent_t> ev;   // pairs (start, end)
     std::vector<int> ev_nest;     // nest of each pair in use
     size_t ev_used = 0;

@@ -294,6 +294,28 @@ def test_profiling_counts_every_gpu_nest():
     g.close()
 
 
+@pytest.mark.parametrize("setup", ["whole", "regions", "fused"])
+def test_profiling_only_the_chosen_nests(setup):
+    say("profiled nests", setup)
+    a = synth.make_problem(65, 33, 33, seed=14)
+    g = ofl.Grid(a)
+    if setup == "regions":
+        ofl.ofl_set_regions(g.handle, 7, [1, 2, 0])
+    if setup == "fused":
+        ofl.ofl_set_fusion(g.handle, ofl.OFL_FUSE_RESIDUAL | ofl.OFL_FUSE_COPYBACK_SWAP)
+    ofl.ofl_set_profiling(g.handle, True)
+    ofl.ofl_set_profiled_nests(g.handle, ofl.OFL_NEST_SWEEP | ofl.OFL_NEST_COPYBACK)
+    ofl.ofl_jacobi_run(g.handle, 5, OMEGA)
+    s = ofl.ofl_get_stats(g.handle)
+    want_c = 0 if setup == "fused" else 5  # a fused copy-back is a buffer exchange: no kernel to time
+    assert list(s.timed_nests) == [5, 0, want_c] and s.kernel_ms[0] > 0
+    ofl.ofl_reset_stats(g.handle)
+    ofl.ofl_set_profiled_nests(g.handle, ofl.OFL_MASK_ALL_GPU)
+    ofl.ofl_jacobi_run(g.handle, 2, OMEGA)
+    assert list(ofl.ofl_get_stats(g.handle).timed_nests) == [2, 2, 0 if setup == "fused" else 2]
+    g.close()
+
+
 def test_device_copy_kernel():
     say("device copy")
     src = torch.arange(1 << 20, dtype=torch.float32, device="cuda")

@@ -81,7 +81,7 @@ def test_run_validates_arguments():
                 lambda: ofl.ofl_jacobi_run(h, 1, float("nan")),
                 lambda: ofl.ofl_set_tile(h, ofl.tile(vec=3)), lambda: ofl.ofl_set_tile(h, ofl.tile(rows=9)),
                 lambda: ofl.ofl_set_tile(h, ofl.tile(kchunk=0)), lambda: ofl.ofl_set_tile(h, ofl.tile(flags=32)),
-                lambda: ofl.ofl_set_fusion(h, 4)):
+                lambda: ofl.ofl_set_fusion(h, 4), lambda: ofl.ofl_set_profiled_nests(h, 8)):
         with pytest.raises(ofl.OflError) as e:
             bad()
         assert e.value.code == ofl.OFL_EINVAL
