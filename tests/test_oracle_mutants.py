@@ -9,6 +9,7 @@ import tempfile
 import pytest
 
 import oracle
+import test_oracle_gemm as gpins
 import test_oracle_pins as pins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
@@ -29,6 +30,13 @@ MUTANTS = [
      "for (int i = 1; i < I - 2; ++i) {\n                double ss = ss_at(I, J, co, p, i, j, k);\n                AT(wrk2"),
     ("residual of new iterate", "    free(wrk2);\n    *gosa = last;", "    oracle_residual(I, J, K, co, p, &last);\n    free(wrk2);\n    *gosa = last;"),
     ("bf16 ties away", "(low == 0x8000u && lsb)", "(low == 0x8000u)"),
+    # matrix product (each stays inside the operands' bounds)
+    ("gemm first term dropped", "for (int k = 0; k < K; ++k)\n                sum +=",
+     "for (int k = 1; k < K; ++k)\n                sum +="),
+    ("gemm last term dropped", "for (int k = 0; k < K; ++k)\n                sum +=",
+     "for (int k = 0; k < K - 1; ++k)\n                sum +="),
+    ("gemm product subtracted", "                sum += a[", "                sum -= a["),
+    ("gemm sum never reset", "            double sum = 0.0;\n            for (int k", "            static double sum = 0.0;\n            for (int k"),
 ]
 
 PIN_CHECKS = [
@@ -45,6 +53,12 @@ PIN_CHECKS = [
     pins.test_residual_of_current_iterate,
     lambda: pins.test_brute_force_matrix_formulation((5, 5, 5)),
     pins.test_bf16_ties_to_even,
+    gpins.test_hand_worked_product,
+    lambda: gpins.test_ones_sum_to_k(3, 5, 7),
+    gpins.test_identity_and_diagonal_scaling,
+    gpins.test_permutation_moves_rows_not_columns,
+    gpins.test_outer_product_and_transpose_identity,
+    gpins.test_small_integer_products_against_brute_force,
 ]
 
 
