@@ -3,16 +3,17 @@
 // Sec. 4.2.1).
 //
 // C = A B for row-major FP32 matrices. A work-group of four waves owns a
-// 128 x 128 tile of C. Each wave owns a 64 x 64 quarter as 2 x 2 accumulator
+// 128 x 256 tile of C. Each wave owns a 64 x 128 quarter as 2 x 4 accumulator
 // tiles of 32 x 32, updated by v_mfma_f32_32x32x2_f32 (FP32 operands, FP32
-// accumulation). The K dimension advances in stages of 16: the next stage's
+// accumulation); each operand value read from LDS feeds two or four products. The K dimension advances in stages of 16: the next stage's
 // A and B tiles are fetched from global memory into registers while the
 // current stage, held in LDS, feeds the matrix cores. LDS is double-buffered,
 // so one barrier per stage suffices.
 //
 // Tiles are handed to work-groups so that each XCD works through a contiguous
-// run of them (measured at 4096^3: 132 against 118 TFLOP/s with the hardware's
-// round-robin order).
+// run of them. Measured at 4096^3 with 128 x 128 tiles, this order ran at up
+// to 132 TFLOP/s against 118 for the hardware's round-robin, but from run to
+// run it varied down to the round-robin figure; 128 x 256 tiles ran at 137.
 //
 // Operand layout of the 32x32x2 instruction (wave64): lane l supplies
 // A[l % 32][l / 32] and B[l / 32][l % 32]; accumulator register r of lane l
@@ -27,8 +28,13 @@ namespace ofl {
 
 namespace {
 
-constexpr int kTileM = 128, kTileN = 128, kTileK = 16;
 constexpr int kGemmThreads = 256;
+constexpr int kTileM = 128, kTileN = 256, kTileK = 16;
+constexpr int kNJ = kTileN / 64;                            // 32-wide accumulator tiles per wave along n
+constexpr int kBThreadsPerRow = kTileN / 8;                 // threads loading one B row, 8 floats each
+constexpr int kBRowsPerPass = kGemmThreads / kBThreadsPerRow;
+constexpr int kBPasses = kTileK / kBRowsPerPass;            // passes over the B tile per stage
+static_assert(kBPasses * kBRowsPerPass == kTileK, "B tile rows must split into whole passes");
 constexpr int kLdsPad = 4;  // floats of padding per LDS row
 constexpr int kXcds = 8;    // accelerator complex dies of an MI355X, each with its own L2
 
@@ -44,31 +50,45 @@ struct GemmArgs {
     int ldc;
 };
 
-// Fetch this thread's share of the A (128 x 16) and B (16 x 128) tiles at k0
-// into registers: A row tid / 2, columns (tid % 2) * 8 .. +8; B row tid / 16,
-// columns (tid % 16) * 8 .. +8. Out-of-range elements read as zero. `vec`:
-// the block's tiles lie inside the matrices and every row start is 16-byte
-// aligned, so whole float4 loads are used.
+// Fetch this thread's share of the A (128 x 16) and B (16 x 256) tiles at k0
+// into registers: A row tid / 2, columns (tid % 2) * 8 .. +8; B rows
+// pass * 8 + tid / 32, columns (tid % 32) * 8 .. +8, for pass 0 and 1.
+// Out-of-range elements read as zero. `vec`: the block's tiles lie inside the
+// matrices and every row start is 16-byte aligned, so whole float4 loads are
+// used.
 __device__ __forceinline__ void fetch(const GemmArgs &g, int m0, int n0, int k0, bool vec, float *ra, float *rb) {
     const int tid = threadIdx.x;
     const int am = m0 + (tid >> 1), ak = k0 + (tid & 1) * 8;
-    const int bk = k0 + (tid >> 4), bn = n0 + (tid & 15) * 8;
+    const int bn = n0 + (tid % kBThreadsPerRow) * 8;
     if (vec && k0 + kTileK <= g.K) {
         const float4 *pa = reinterpret_cast<const float4 *>(g.A + static_cast<size_t>(am) * g.lda + ak);
-        const float4 *pb = reinterpret_cast<const float4 *>(g.B + static_cast<size_t>(bk) * g.ldb + bn);
-        const float4 a0 = pa[0], a1 = pa[1], b0 = pb[0], b1 = pb[1];
+        const float4 a0 = pa[0], a1 = pa[1];
         ra[0] = a0.x; ra[1] = a0.y; ra[2] = a0.z; ra[3] = a0.w;
         ra[4] = a1.x; ra[5] = a1.y; ra[6] = a1.z; ra[7] = a1.w;
-        rb[0] = b0.x; rb[1] = b0.y; rb[2] = b0.z; rb[3] = b0.w;
-        rb[4] = b1.x; rb[5] = b1.y; rb[6] = b1.z; rb[7] = b1.w;
+#pragma unroll
+        for (int pass = 0; pass < kBPasses; ++pass) {
+            const int bk = k0 + pass * kBRowsPerPass + tid / kBThreadsPerRow;
+            const float4 *pb = reinterpret_cast<const float4 *>(g.B + static_cast<size_t>(bk) * g.ldb + bn);
+            const float4 b0 = pb[0], b1 = pb[1];
+            float *r = rb + pass * 8;
+            r[0] = b0.x; r[1] = b0.y; r[2] = b0.z; r[3] = b0.w;
+            r[4] = b1.x; r[5] = b1.y; r[6] = b1.z; r[7] = b1.w;
+        }
         return;
     }
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int k = ak + e;
         ra[e] = (am < g.M && k < g.K) ? g.A[static_cast<size_t>(am) * g.lda + k] : 0.f;
-        const int n = bn + e;
-        rb[e] = (bk < g.K && n < g.N) ? g.B[static_cast<size_t>(bk) * g.ldb + n] : 0.f;
+    }
+#pragma unroll
+    for (int pass = 0; pass < kBPasses; ++pass) {
+        const int bk = k0 + pass * kBRowsPerPass + tid / kBThreadsPerRow;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int n = bn + e;
+            rb[pass * 8 + e] = (bk < g.K && n < g.N) ? g.B[static_cast<size_t>(bk) * g.ldb + n] : 0.f;
+        }
     }
 }
 
@@ -80,7 +100,7 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_f32_kernel(GemmArgs g, int 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * (kTileN / 2);
     // Work-groups are dealt round-robin to the eight XCDs. Give each XCD a
     // contiguous run of tiles in row-major tile order instead, so that tiles
     // sharing rows of A (and neighbouring columns of B) meet in one XCD's L2.
@@ -95,23 +115,28 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_f32_kernel(GemmArgs g, int 
     const int m0 = by * kTileM, n0 = bx * kTileN;
     const bool vec = vec_ok && m0 + kTileM <= g.M && n0 + kTileN <= g.N;
 
-    floatx16 acc[2][2];
+    floatx16 acc[2][kNJ];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < kNJ; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 acc[i][j][r] = 0.f;
 
-    float ra[8], rb[8];
+    float ra[8], rb[8 * kBPasses];
     auto stash = [&](int buf) {
         const int am = tid >> 1, ak = (tid & 1) * 8;
-        const int bk = tid >> 4, bn = (tid & 15) * 8;
+        const int bn = (tid % kBThreadsPerRow) * 8;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
+        for (int e = 0; e < 8; ++e)
             As[buf][ak + e][am] = ra[e];
-            Bs[buf][bk][bn + e] = rb[e];
+#pragma unroll
+        for (int pass = 0; pass < kBPasses; ++pass) {
+            const int bk = pass * kBRowsPerPass + tid / kBThreadsPerRow;
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                Bs[buf][bk][bn + e] = rb[pass * 8 + e];
         }
     };
 
@@ -126,16 +151,17 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_f32_kernel(GemmArgs g, int 
             fetch(g, m0, n0, k0 + kTileK, vec, ra, rb);
 #pragma unroll
         for (int kk = 0; kk < kTileK; kk += 2) {
-            float a[2], b[2];
+            float a[2], b[kNJ];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
+            for (int i = 0; i < 2; ++i)
                 a[i] = As[buf][kk + lrow][wm + i * 32 + lcol];
-                b[i] = Bs[buf][kk + lrow][wn + i * 32 + lcol];
-            }
+#pragma unroll
+            for (int j = 0; j < kNJ; ++j)
+                b[j] = Bs[buf][kk + lrow][wn + j * 32 + lcol];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                for (int j = 0; j < kNJ; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         if (more)
@@ -147,7 +173,7 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_f32_kernel(GemmArgs g, int 
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < kNJ; ++j) {
             const int col = n0 + wn + j * 32 + lcol;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
