@@ -192,8 +192,16 @@ def _max_rel(out, ref) -> float:
     refs = ref if isinstance(ref, tuple) else (ref,)
     worst = 0.0
     for o, r in zip(outs, refs):
+        if o is None or r is None:
+            if o is not r:
+                return float("inf")
+            continue
         o = np.asarray(o, dtype=np.float64)
         r = np.asarray(r, dtype=np.float64)
+        if o.shape != r.shape:
+            return float("inf")
+        if r.size == 0:
+            continue
         scale = max(float(np.max(np.abs(r))), 1e-300)
         worst = max(worst, float(np.max(np.abs(o - r))) / scale)
     return worst
