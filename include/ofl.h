@@ -256,7 +256,9 @@ typedef struct ofl_stats {
 } ofl_stats;
 
 /* Profiling on: each GPU nest is bracketed by HIP events on the grid's stream
- * and its time is added to kernel_ms at the next synchronisation. */
+ * and its time is added to kernel_ms at the next synchronisation. A nest split
+ * into regions is bracketed as a whole; under the per-iteration placement it is
+ * not timed, since its transfers sit between its launches. */
 int ofl_set_profiling(ofl_grid *g, int on);
 
 /* Which nests profiling brackets (bit n: nest n, as in the offload mask;
