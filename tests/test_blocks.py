@@ -94,3 +94,16 @@ def test_trials_score_wrong_and_unbuildable_blocks_as_infinite():
     assert all(t.status == "wrong" for t in res["trials"] if t.gene) and res["best"].gene == 0
     res = fb.trial_blocks(prog, args(), repeats=1, gpu_routines={"gemm_f32": unbuildable})
     assert all(t.status == "not buildable" for t in res["trials"] if t.gene) and res["best"].gene == 0
+
+
+def test_program_driver_tries_blocks_then_loops():
+    from paper_2011_03602_amd.offload import offload_program
+
+    rep = offload_program(MLP, args(), block_repeats=1, gpu_routines={"gemm_f32": np.matmul})
+    assert len(rep["blocks"]["found"]) == 3 and rep["blocks"]["best_gene"] in range(8)
+    assert rep["loops"]["offloadable"] is False and "iteration loop" in rep["loops"]["reason"]
+    relax = open(os.path.join(HERE, "programs", "relax.py")).read()
+    rep = offload_program(relax, {}, search_loops=False)
+    assert rep["blocks"] is None
+    assert rep["loops"]["offloadable"] and rep["loops"]["gene_bits"] == 9
+    assert rep["loops"]["binding"]["u"] == "p"

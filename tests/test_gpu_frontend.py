@@ -79,3 +79,22 @@ def test_search_on_the_programs_data():
     err, u = fe.offload(prog, args, r.gene)
     p_ref, g_ref = oracle.jacobi(arrays, 3, float(OMEGA))
     assert p_rel_err(u, p_ref) <= TOL_P_F32 and rel_err(err, g_ref) <= TOL_GOSA_F32
+
+
+def test_program_driver_on_the_gpu():
+    say("program driver: blocks then loops")
+    import paper_2011_03602_amd as ofl
+    from paper_2011_03602_amd.offload import offload_program
+
+    arrays = synth.make_problem(40, 30, 20, seed=2)
+    rep = offload_program(RELAX, program_args(arrays, 3), ga=ofl.ga_params(population=6, generations=2, seed=1,
+                                                                           repeats=1))
+    assert rep["blocks"] is None and rep["loops"]["offloadable"]
+    assert rep["loops"]["best_ms"] > 0 and rep["loops"]["gene"] < (1 << 9)
+    mlp = open(os.path.join(HERE, "programs", "mlp.py")).read()
+    rng = np.random.default_rng(0)
+    a = {"x": rng.uniform(-1, 1, (256, 128)).astype(np.float32), "w1": rng.uniform(-1, 1, (128, 128)).astype(np.float32),
+         "w2": rng.uniform(-1, 1, (128, 64)).astype(np.float32), "w3": rng.uniform(-1, 1, (64, 8)).astype(np.float32)}
+    rep = offload_program(mlp, a, block_repeats=1)
+    assert len(rep["blocks"]["found"]) == 3 and all(s == "ok" for _, _, s in rep["blocks"]["trials"])
+    assert rep["loops"]["offloadable"] is False
