@@ -189,6 +189,37 @@ def run_batch(ofl, probs, fmt, steps, warmup, tune, iters=ITERS):
     }
 
 
+def run_small(ofl):
+    """33x33x65, 50 iterations, genes 000 and 111 (hoisted): per-iteration
+    latency of the small grid, which is bound by kernel launches."""
+    import torch
+
+    import synth
+
+    I, J, K, iters = 33, 33, 65, 50
+    arrays = synth.make_problem(I, J, K)
+    out = {}
+    for mask in (ofl.OFL_MASK_ALL_CPU, ofl.OFL_MASK_ALL_GPU):
+        g = ofl.Grid(arrays, torch_memory=True)
+        ofl.ofl_set_offload_mask(g.handle, mask, ofl.OFL_XFER_HOISTED)
+        ofl.ofl_data_enter(g.handle)
+        ofl.ofl_jacobi_run(g.handle, 5, OMEGA)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ofl.ofl_jacobi_run(g.handle, iters, OMEGA)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = ofl.ofl_get_stats(g.handle)
+        ofl.ofl_data_exit(g.handle)
+        g.close()
+        launches = sum(int(x) for x in st.gpu_regions)
+        out[format(mask, "03b")] = {"us_per_iteration": round(dt / iters * 1e6, 2),
+                                    "glups": round(interior(I, J, K) * iters / dt / 1e9, 4),
+                                    "kernel_nests_per_iteration": round(launches / (iters + 5), 2)}
+        log(f"33x33x65 gene {mask:03b}: {dt / iters * 1e6:.1f} us per iteration")
+    return out
+
+
 def run_masks(ofl, steps_unused=None):
     """Every gene x placement on 129x129x257 for 200 iterations, end to end
     (transfers included, host arrays in pinned memory), against the all-CPU
@@ -224,11 +255,13 @@ def run_masks(ofl, steps_unused=None):
                          "gosa_rel_err": abs(gosa - g_ref) / abs(g_ref)})
             log(f"mask {mask:03b} {mode_name}: {dt:.3f} s")
             g.close()
+    small = run_small(ofl)
     cpu = {r["placement"]: r["seconds"] for r in rows if r["mask"] == 0}
     for r in rows:
         r["speedup_vs_all_cpu_gene"] = round(cpu[r["placement"]] / r["seconds"], 2)
         r["speedup_vs_oracle"] = round(t_oracle / r["seconds"], 2)
-    return {"config": "129x129x257 FP32, 200 iterations, every gene x placement", "oracle_seconds": round(t_oracle, 3),
+    return {"config": "129x129x257 FP32, 200 iterations, every gene x placement", "small_33x33x65": small,
+            "oracle_seconds": round(t_oracle, 3),
             "host_threads_cpu_nests": os.environ.get("OFL_CPU_THREADS") or os.environ.get("OMP_NUM_THREADS")
             or os.cpu_count(), "rows": rows}
 
