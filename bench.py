@@ -466,6 +466,23 @@ def run_precision(ofl):
             "gosa_oracle": g_ref, "rows": out}
 
 
+def tune_headline(ofl, arrays, fmt):
+    """The GA tile search (population 16, 12 generations, 5 iterations per
+    probe, median of 3) on the headline grid; returns the tile it picks and
+    the search's own figures."""
+    g = ofl.Grid(arrays, coef_format=fmt, torch_memory=True)
+    ofl.ofl_set_offload_mask(g.handle, ofl.OFL_MASK_ALL_GPU, ofl.OFL_XFER_HOISTED)
+    default = ofl.ofl_get_tile(g.handle)
+    t0 = time.perf_counter()
+    r = ofl.ofl_grid_tune(g.handle, ofl.ga_params())
+    dt = time.perf_counter() - t0
+    g.close()
+    log(f"GA tile search ({'f32' if fmt == 0 else 'bf16'}): {r.best.as_dict()} in {dt:.1f} s")
+    return r.best, {"tile": r.best.as_dict(), "probe_ms": round(r.best_ms, 3), "genes_measured": r.evaluated,
+                    "genes_rejected": r.rejected, "search_seconds": round(dt, 1),
+                    "default_tile": default.as_dict()}
+
+
 def cpu_program(ofl, arrays, iters):
     """The library's all-CPU gene (the original program's loops, on the host
     threads) on a bounded sample of the headline workload."""
@@ -510,6 +527,8 @@ def main():
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--batch-grids", type=int, default=64)
     ap.add_argument("--tune-batch", action="store_true", help="run the GA tile search before the batched run")
+    ap.add_argument("--tune", action="store_true",
+                    help="also run the GA tile search on the headline grid and report the tuned tile's run")
     ap.add_argument("--oracle-iters", type=int, default=10)
     ap.add_argument("--profile-only", default=None,
                     help="headline|bf16|batch|copy|gemm: run just that under a profiler, print no JSON")
@@ -643,6 +662,13 @@ def main():
                 "speedup_vs_f32": round(bf["glups"] / head["glups"], 3),
             }
         }
+        if args.tune:
+            for name, fmt in (("ga_tuned_f32", ofl.OFL_COEF_F32), ("ga_tuned_bf16_offset", ofl.OFL_COEF_BF16_OFFSET)):
+                best, info = tune_headline(ofl, arrays, fmt)
+                tr = run_single(ofl, arrays, fmt, args.steps, args.warmup, tile=best)
+                info.update(glups=round(tr["glups"], 3), ms_per_step=round(tr["ms_per_step"], 3),
+                            sweep_avg_us=round(tr["nest_ms_avg"][0] * 1e3, 2))
+                out["variants"][name] = info
         fuse = ofl.OFL_FUSE_RESIDUAL | ofl.OFL_FUSE_COPYBACK_SWAP
         for name, fmt, ib in (("fused_f32", ofl.OFL_COEF_F32, 56), ("fused_bf16_offset", ofl.OFL_COEF_BF16_OFFSET, 32)):
             log(f"{name} variant (sweep with the residual folded in, copy-back as a buffer exchange)")

@@ -26,11 +26,17 @@ int cpu_threads() {
     return hw ? static_cast<int>(hw) : 1;
 }
 
-// f(k) for k in [lo, hi), split into contiguous ranges over the host threads.
+// Starting a thread costs tens of microseconds: below this many points per
+// thread a small grid runs faster on fewer threads (or on the caller's).
+constexpr long long kMinPointsPerThread = 1 << 14;
+
+// f(k) for k in [lo, hi), split into contiguous ranges over the host threads;
+// each index stands for `work` points.
 template <class F>
-void parallel_planes(int lo, int hi, F &&f) {
+void parallel_planes(int lo, int hi, long long work, F &&f) {
     const int n = hi - lo;
-    const int nt = std::max(1, std::min(cpu_threads(), n));
+    const long long by_work = std::max<long long>(1, static_cast<long long>(n) * work / kMinPointsPerThread);
+    const int nt = static_cast<int>(std::max<long long>(1, std::min<long long>({cpu_threads(), n, by_work})));
     if (nt == 1) {
         for (int k = lo; k < hi; ++k)
             f(k);
@@ -84,7 +90,7 @@ template <class Co>
 void sweep_impl(int I, int J, int K, const Co &co, const float *p, float *wrk2, float omega) {
     const ptrdiff_t dj = I;                        // offset of the j+1 neighbour
     const ptrdiff_t dk = static_cast<ptrdiff_t>(I) * J;  // offset of the k+1 neighbour
-    parallel_planes(1, K - 1, [&](int k) {
+    parallel_planes(1, K - 1, static_cast<long long>(I) * J, [&](int k) {
         for (int j = 1; j < J - 1; ++j) {
             for (int i = 1; i < I - 1; ++i) {
                 const ptrdiff_t c = i + dj * j + dk * k;
@@ -124,7 +130,7 @@ double cpu_residual(int I, int J, int K, const float *p, const float *wrk2, floa
     const size_t sI = static_cast<size_t>(I);
     const size_t sIJ = sI * static_cast<size_t>(J);
     std::vector<double> plane(static_cast<size_t>(K), 0.0);
-    parallel_planes(1, K - 1, [&](int k) {
+    parallel_planes(1, K - 1, static_cast<long long>(I) * J, [&](int k) {
         double acc = 0.0;
         for (int j = 1; j < J - 1; ++j)
             for (int i = 1; i < I - 1; ++i) {
@@ -144,7 +150,7 @@ double cpu_residual(int I, int J, int K, const float *p, const float *wrk2, floa
 void cpu_copyback(int I, int J, int K, const float *wrk2, float *p) {
     const size_t sI = static_cast<size_t>(I);
     const size_t sIJ = sI * static_cast<size_t>(J);
-    parallel_planes(1, K - 1, [&](int k) {
+    parallel_planes(1, K - 1, static_cast<long long>(I) * J, [&](int k) {
         for (int j = 1; j < J - 1; ++j) {
             const size_t c = 1 + sI * j + sIJ * k;
             std::memcpy(p + c, wrk2 + c, sizeof(float) * static_cast<size_t>(I - 2));
@@ -154,7 +160,7 @@ void cpu_copyback(int I, int J, int K, const float *wrk2, float *p) {
 
 void cpu_encode_bf16(const float *x, size_t n, float bias, uint16_t *q) {
     const int nt = static_cast<int>(std::max<size_t>(1, std::min<size_t>(static_cast<size_t>(cpu_threads()), n / 65536 + 1)));
-    parallel_planes(0, nt, [&](int t) {
+    parallel_planes(0, nt, static_cast<long long>(n / static_cast<size_t>(nt)), [&](int t) {
         const size_t a = n * static_cast<size_t>(t) / static_cast<size_t>(nt);
         const size_t b = n * static_cast<size_t>(t + 1) / static_cast<size_t>(nt);
         for (size_t u = a; u < b; ++u)
