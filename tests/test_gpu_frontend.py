@@ -98,3 +98,30 @@ def test_program_driver_on_the_gpu():
     rep = offload_program(mlp, a, block_repeats=1)
     assert len(rep["blocks"]["found"]) == 3 and all(s == "ok" for _, _, s in rep["blocks"]["trials"])
     assert rep["loops"]["offloadable"] is False
+
+
+def test_c_program_offloaded_matches_itself_and_the_oracle(tmp_path):
+    say("C front end on the GPU")
+    from paper_2011_03602_amd import cfront as cf
+
+    src = open(os.path.join(HERE, "programs", "relax.c")).read()
+    names = {"a0": "east", "a1": "north", "a2": "top", "a3": "inv_diag", "b0": "cxy", "b1": "cyz", "b2": "cxz",
+             "c0": "west", "c1": "south", "c2": "bottom", "bnd": "keep", "wrk1": "rhs", "p": "v"}
+    cp = cf.analyse(src)
+
+    def values(arrays, sweeps):
+        vals = {names[k]: np.ascontiguousarray(arrays[k], dtype=np.float32).copy() for k in names}
+        vals.update(sweeps=sweeps, relax=float(OMEGA))
+        return vals
+
+    small = synth.make_problem(12, 9, 8, seed=21)
+    ref_vals = values(small, 3)
+    res_c = cf.run_c(cp, ref_vals, str(tmp_path))
+    for gene in (0b001_001_001, 0b010_100_001, 0b100_010_010):
+        vals = values(small, 3)
+        res, v = cf.offload(cp, vals, gene)
+        assert p_rel_err(v, ref_vals["v"]) <= TOL_P_F32 and rel_err(res, res_c) <= TOL_GOSA_F32
+    big = synth.make_problem(70, 40, 33, seed=22)
+    p_ref, g_ref = oracle.jacobi(big, 6, float(OMEGA))
+    res, v = cf.offload(cp, values(big, 6), 0b001_001_001)
+    assert p_rel_err(v, p_ref) <= TOL_P_F32 and rel_err(res, g_ref) <= TOL_GOSA_F32
