@@ -131,14 +131,15 @@ def run_single(ofl, arrays, fmt, steps, warmup, tile=None, profile=True, iters=I
     return res
 
 
-def run_batch(ofl, probs, fmt, steps, warmup, tune, iters=ITERS):
+def run_batch(ofl, probs, fmt, steps, warmup, tune, iters=ITERS, row_align=0):
     """The uneven grids in one batch: plain and fused graph runs against the
-    same grids run one after another with single-grid calls."""
+    same grids run one after another with single-grid calls. ``row_align``:
+    the grids' device row alignment (4: packed rows in the batch)."""
     import torch
 
     n_grids = len(probs)
     total_lups = sum(interior(*shape) for shape, _ in probs) * iters
-    grids = [ofl.Grid(arr, coef_format=fmt) for _, arr in probs]
+    grids = [ofl.Grid(arr, coef_format=fmt, row_align=row_align) for _, arr in probs]
     for g in grids:
         ofl.ofl_data_enter(g.handle)
     b = ofl.ofl_batch_create([g.handle for g in grids])
@@ -185,6 +186,7 @@ def run_batch(ofl, probs, fmt, steps, warmup, tune, iters=ITERS):
         "ms_batched_fused": round(1e3 * dt_fused, 3),
         "ms_sequential": round(1e3 * dt_seq, 3),
         "tile": tile_used,
+        "row_align": row_align,
         "tuner": tuned,
     }
 
@@ -527,9 +529,11 @@ def main():
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--batch-grids", type=int, default=64)
     ap.add_argument("--tune-batch", action="store_true", help="run the GA tile search before the batched run")
+    ap.add_argument("--batch-row-align", type=int, default=4,
+                    help="device row alignment of the batched grids (4: packed rows; 0: 128-byte rows)")
     ap.add_argument("--tune", action="store_true",
                     help="also run the GA tile search on the headline grid and report the tuned tile's run")
-    ap.add_argument("--oracle-iters", type=int, default=10)
+    ap.add_argument("--oracle-iters", type=int, default=50)
     ap.add_argument("--profile-only", default=None,
                     help="headline|bf16|batch|copy|gemm: run just that under a profiler, print no JSON")
     ap.add_argument("--profile-iters", type=int, default=ITERS,
@@ -594,7 +598,7 @@ def main():
             run_single(ofl, arrays, ofl.OFL_COEF_BF16_OFFSET, args.steps, args.warmup, profile=False, iters=it)
         elif args.profile_only == "batch":
             run_batch(ofl, synth.make_batch(args.batch_grids), ofl.OFL_COEF_F32, args.steps, args.warmup, False,
-                      iters=it)
+                      iters=it, row_align=args.batch_row_align)
         else:
             raise SystemExit(f"unknown --profile-only {args.profile_only}")
         log("profile run done")
@@ -685,7 +689,8 @@ def main():
             probs = synth.make_batch(args.batch_grids)
             for name, fmt in (("batched_f32", ofl.OFL_COEF_F32), ("batched_bf16_offset", ofl.OFL_COEF_BF16_OFFSET)):
                 log(f"{name} variant")
-                out["variants"][name] = run_batch(ofl, probs, fmt, max(1, args.steps // 2), 1, args.tune_batch)
+                out["variants"][name] = run_batch(ofl, probs, fmt, max(1, args.steps // 2), 1, args.tune_batch,
+                                                  row_align=args.batch_row_align)
             del probs
     if not args.skip_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(arrays, args.oracle_iters)

@@ -100,9 +100,14 @@ typedef struct ofl_grid_desc {
                                aligned, at least ofl_grid_device_bytes() bytes; NULL: hipMalloc */
     size_t dev_arena_bytes; /* size of dev_arena */
     int device;             /* HIP device ordinal; -1: the device current at creation */
+    int row_align;          /* elements every device row is padded to: 0 for a 128-byte line (32 FP32 or
+                               64 bfloat16 elements), else 4, 8, 16 or 32. Short rows waste less memory
+                               with a small alignment, and a batch runs such grids in packed rows
+                               (ofl_batch_create). Results do not depend on it. */
 } ofl_grid_desc;
 
-/* Device bytes a grid of this shape and format needs (arena sizing).
+/* Device bytes a grid of this shape and format needs (arena sizing), with the
+ * default row alignment; a smaller desc.row_align needs no more.
  * Returns OFL_EINVAL for a dimension below 3 or an unknown format. */
 int ofl_grid_device_bytes(int I, int J, int K, int coef_format, size_t *bytes);
 

@@ -44,7 +44,7 @@ class OflGridDesc(ctypes.Structure):
         ("coef_format", ctypes.c_int), ("sum_mode", ctypes.c_int),
         ("p", _FP), ("wrk2", _FP), ("coef", _FP * 12),
         ("stream", ctypes.c_void_p), ("dev_arena", ctypes.c_void_p),
-        ("dev_arena_bytes", ctypes.c_size_t), ("device", ctypes.c_int),
+        ("dev_arena_bytes", ctypes.c_size_t), ("device", ctypes.c_int), ("row_align", ctypes.c_int),
     ]
 
 
@@ -461,10 +461,12 @@ class Grid:
     PyTorch when ``pinned``), which the library borrows for the handle's life.
     ``torch_memory``: take the grid's device block from PyTorch's allocator and
     launch on a PyTorch stream (needs a GPU); otherwise the library allocates.
+    ``row_align``: elements each device row is padded to (0: 128-byte rows).
     """
 
     def __init__(self, arrays: Dict[str, np.ndarray], coef_format: int = OFL_COEF_F32,
-                 sum_mode: int = OFL_SUM_F64, torch_memory: bool = False, pinned: bool = False):
+                 sum_mode: int = OFL_SUM_F64, torch_memory: bool = False, pinned: bool = False,
+                 row_align: int = 0):
         p = np.asarray(arrays["p"])
         if p.ndim != 3:
             raise ValueError("arrays must be 3-D (K, J, I)")
@@ -488,6 +490,7 @@ class Grid:
         for n, name in enumerate(COEF_NAMES):
             desc.coef[n] = self.host[name].ctypes.data_as(_FP)
         desc.device = -1
+        desc.row_align = row_align
         self.stream = None
         if torch_memory:
             import torch

@@ -72,6 +72,7 @@ void batch_upload_views(ofl_batch *b) {
     for (size_t g = 0; g < n; ++g) {
         views[g] = b->grids[g]->view;
         views[g].partials = static_cast<double *>(b->d_partials) + b->partial_base[g];
+        views[g].nseg = b->nseg.empty() ? 0 : b->nseg[g];
         swapped[g] = views[g];
         std::swap(swapped[g].p, swapped[g].wrk2);
     }
@@ -106,6 +107,31 @@ int batch_auto_vec(int I) {
     return best;
 }
 
+// Packed rows for a grid whose rows fill few of a wave's lanes. A wave then
+// covers 64 * vec consecutive points of a plane across row ends, so its lanes
+// idle only on the two boundary columns and the row padding, and a row no
+// longer pays partial HBM granules at both of its ends. Worth it only when the
+// rows are packed tightly (a small desc.row_align): with 128-byte rows the
+// padding would be loaded and the lanes idle as before. Chosen when it keeps
+// more lanes busy than one row per wave; never for waves marching along j.
+bool batch_packed(int I, int J, int pitch, const TileCfg &t, int *vec, int *nseg) {
+    if (t.flags & OFL_TILE_MARCH_J)
+        return false;
+    const int vrow = t.vec > 0 ? t.vec : batch_auto_vec(I);
+    const int vpk = t.vec > 0 ? t.vec : 4;
+    if (pitch % vpk != 0)
+        return false;
+    const int span_row = kWave * vrow, span_pk = kWave * vpk;
+    const long long segs = packed_nseg(J, pitch, vpk);
+    const double util_row = static_cast<double>(I - 2) / (static_cast<double>(span_row) * itiles(I, vrow));
+    const double util_pk = static_cast<double>(I - 2) * (J - 2) / (static_cast<double>(segs) * span_pk);
+    if (util_pk <= util_row * 1.02 || segs > 0x7fffffffLL / 4)
+        return false;
+    *vec = vpk;
+    *nseg = static_cast<int>(segs);
+    return true;
+}
+
 void batch_build_tables(ofl_batch *b) {
     if (b->tables_ready)
         return;
@@ -130,18 +156,33 @@ void batch_build_tables(ofl_batch *b) {
     std::vector<int> range(static_cast<size_t>(n) + 1, 0);
     std::vector<int> count(static_cast<size_t>(n), 0);
     const int rows_per_item = kRowsPerWaveItem * (kResidualThreads / kWave);
+    b->nseg.assign(static_cast<size_t>(n), 0);
     for (int g : order) {
         const ofl_grid *q = b->grids[static_cast<size_t>(g)];
         TileCfg t = b->tile;
-        t.vec = b->tile.vec > 0 ? b->tile.vec : batch_auto_vec(q->I);
+        int pvec = 0, nseg = 0;
+        const bool packed = batch_packed(q->I, q->J, q->lay.pitch, b->tile, &pvec, &nseg);
+        t.vec = packed ? pvec : (b->tile.vec > 0 ? b->tile.vec : batch_auto_vec(q->I));
         const int c = t.vec == 1 ? 0 : (t.vec == 2 ? 1 : 2);
         int nti, nfb, nmc;
-        sweep_shape(q->I, q->J, q->K, t, &nti, &nfb, &nmc);
+        if (packed) {
+            // one "line" per segment; the kernels find the segment from fblock
+            nti = 1;
+            nfb = (nseg + t.rows - 1) / t.rows;
+            nmc = (q->K - 2 + t.kchunk - 1) / t.kchunk;
+            b->nseg[static_cast<size_t>(g)] = nseg;
+        } else {
+            sweep_shape(q->I, q->J, q->K, t, &nti, &nfb, &nmc);
+        }
         for (int mc = 0; mc < nmc; ++mc)
             for (int fb = 0; fb < nfb; ++fb)
                 for (int it = 0; it < nti; ++it)
                     sitems_by[c].push_back({g, it, fb, mc});
-        const int nrt = nti * (q->J - 2) * (q->K - 2);
+        const long long nrt_l = packed ? static_cast<long long>(nseg) * (q->K - 2)
+                                       : static_cast<long long>(nti) * (q->J - 2) * (q->K - 2);
+        if (nrt_l > 0x7fffffffLL)
+            fail(OFL_EINVAL, "a batched grid has too many row tiles");
+        const int nrt = static_cast<int>(nrt_l);
         int slot = 0;
         for (int first = 0; first < nrt; first += rows_per_item) {
             ritems_by[c].push_back({g, first, std::min(rows_per_item, nrt - first), slot});

@@ -30,6 +30,7 @@ struct ofl_batch {
     int r_off[3] = {}, r_cnt[3] = {};  // residual/copy-back items per class
 
     std::vector<int> partial_base;  // per grid, its first residual partial
+    std::vector<int> nseg;          // per grid, segments per plane in packed rows (0: one row per wave)
 
     hipGraphExec_t exec = nullptr;
     int graph_iters = -1;
@@ -47,6 +48,8 @@ void batch_finish(ofl_batch *b, int iters, double *gosa_out);
 void batch_mark_done(ofl_batch *b, int iters);
 void batch_after_run(ofl_batch *b, int iters);
 void batch_upload_views(ofl_batch *b);
+int batch_auto_vec(int I);
+bool batch_packed(int I, int J, int pitch, const ofl::TileCfg &t, int *vec, int *nseg);
 int batch_auto_vec(int I);
 bool batch_auto_vec_tile(const ofl_tile &t);
 

@@ -37,17 +37,22 @@ void hip_check(hipError_t e, const char *what) {
         throw Error(OFL_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-Layout make_layout(int I, int J, int K, int coef_format) {
+Layout make_layout(int I, int J, int K, int coef_format, int row_align) {
     Layout L;
     L.I = I;
     L.J = J;
     L.K = K;
-    // Rows start on 128-byte boundaries for every stored element size: 32
-    // FP32 or 64 bfloat16 elements. (A 576-byte bfloat16 row would start every
-    // other row mid-line, and a wave's 512-byte read would then touch five
-    // cache lines instead of four.)
-    L.pitch = round_up(I, coef_format == OFL_COEF_F32 ? kPitchAlign : 2 * kPitchAlign);
+    // By default rows start on 128-byte boundaries for every stored element
+    // size: 32 FP32 or 64 bfloat16 elements. (A 576-byte bfloat16 row would
+    // start every other row mid-line, and a wave's 512-byte read would then
+    // touch five cache lines instead of four.) A smaller row alignment packs
+    // short rows tighter; it stays a multiple of 4 elements, so every vector
+    // load of up to 4 elements starts on its own size.
+    const int align = row_align > 0 ? row_align : (coef_format == OFL_COEF_F32 ? kPitchAlign : 2 * kPitchAlign);
+    L.pitch = round_up(I, align);
     L.plane = static_cast<size_t>(L.pitch) * J;
+    if (row_align > 0)
+        L.plane = align_up(L.plane, static_cast<size_t>(kSegAlign));
     L.elems = L.plane * K;
     L.coef_elem = coef_format == OFL_COEF_F32 ? 4 : 2;
     size_t off = 0;
@@ -158,7 +163,7 @@ void grid_ensure_device(ofl_grid *g) {
         fail(OFL_EINVAL, "desc.device is not a valid HIP device ordinal");
     hip_check(hipSetDevice(dev), "hipSetDevice");
     g->device = dev;
-    g->lay = make_layout(g->I, g->J, g->K, g->fmt);
+    g->lay = make_layout(g->I, g->J, g->K, g->fmt, g->row_align);
     if (g->arena) {
         if (g->arena_bytes < g->lay.total)
             fail(OFL_ENOMEM, "dev_arena is smaller than ofl_grid_device_bytes()");
@@ -193,6 +198,7 @@ void grid_ensure_device(ofl_grid *g) {
     v.J = g->J;
     v.K = g->K;
     v.pitch = g->lay.pitch;
+    v.nseg = 0;
     v.plane = static_cast<long long>(g->lay.plane);
     v.partials = reinterpret_cast<double *>(g->block + g->lay.partials_off);
     v.gosa = reinterpret_cast<double *>(g->block + g->lay.gosa_off);
@@ -651,14 +657,16 @@ void grid_exec(ofl_grid *g, const std::vector<Xfer> &xs) {
         if (x.dir == 0) {
             hip_check(hipMemcpyAsync(staging, host_src(g, x.array), bytes, hipMemcpyHostToDevice, g->stream),
                       "hipMemcpyAsync(host->device)");
-            launch_pack(staging, arr, g->I, g->J, g->K, g->lay.pitch, static_cast<int>(eb), g->stream);
+            launch_pack(staging, arr, g->I, g->J, g->K, g->lay.pitch, static_cast<long long>(g->lay.plane),
+                        static_cast<int>(eb), g->stream);
             if (x.array == OFL_ARR_P || x.array == OFL_ARR_WRK2)
                 g->wrk2_boundary_ok = false;
             g->stats.h2d_count += 1;
             g->stats.h2d_bytes += bytes;
         } else {
             void *dst = x.array == OFL_ARR_P ? static_cast<void *>(g->p) : static_cast<void *>(g->wrk2);
-            launch_unpack(arr, staging, g->I, g->J, g->K, g->lay.pitch, static_cast<int>(eb), g->stream);
+            launch_unpack(arr, staging, g->I, g->J, g->K, g->lay.pitch, static_cast<long long>(g->lay.plane),
+                          static_cast<int>(eb), g->stream);
             hip_check(hipMemcpyAsync(dst, staging, bytes, hipMemcpyDeviceToHost, g->stream),
                       "hipMemcpyAsync(device->host)");
             g->stats.d2h_count += 1;
@@ -765,6 +773,9 @@ int ofl_grid_create(const ofl_grid_desc *d, ofl_grid **out) {
         for (int a = 0; a < kNCoef; ++a)
             if (!d->coef[a])
                 fail(OFL_EINVAL, "every coefficient array must be given");
+        if (d->row_align != 0 && d->row_align != 4 && d->row_align != 8 && d->row_align != 16 &&
+            d->row_align != 32)
+            fail(OFL_EINVAL, "row_align must be 0, 4, 8, 16 or 32");
         if (d->dev_arena && (reinterpret_cast<uintptr_t>(d->dev_arena) % 256) != 0)
             fail(OFL_EINVAL, "dev_arena must be 256-byte aligned");
         std::unique_ptr<ofl_grid> g(new ofl_grid);
@@ -782,6 +793,7 @@ int ofl_grid_create(const ofl_grid_desc *d, ofl_grid **out) {
         g->arena = d->dev_arena;
         g->arena_bytes = d->dev_arena_bytes;
         g->want_device = d->device;
+        g->row_align = d->row_align;
         g->tile = default_tile(d->I);
         if (g->fmt != OFL_COEF_F32)
             encode_bf16(g.get());

@@ -22,6 +22,7 @@ struct ofl_grid {
     void *arena = nullptr;
     size_t arena_bytes = 0;
     int want_device = -1;
+    int row_align = 0;  // desc.row_align: 0 for 128-byte rows
 
     unsigned mask = OFL_MASK_ALL_GPU;
     int mode = OFL_XFER_HOISTED;

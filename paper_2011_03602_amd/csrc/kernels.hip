@@ -127,14 +127,15 @@ __device__ __forceinline__ void load_bf16(const uint16_t *ptr, float bias, float
 // whole step: issue_prow() starts the vector load and the halo load,
 // finish_prow() takes the inner neighbours from the adjacent lanes and the
 // two wave-edge neighbours from the halo value. The halo load is branch-free:
-// lane 63 reads the element after the tile, every other lane the element
-// before it (one shared cache line). For the first tile of a row that element
-// is row padding or the array's front guard; it only feeds i = 0, which is
-// never stored.
+// lane 63 reads the element after the tile (hr), every other lane the element
+// before it (hl, one shared cache line). For the first tile of a row that
+// element is row padding or the array's front guard; it only feeds i = 0,
+// which is never stored.
 template <int VEC>
-__device__ __forceinline__ void issue_prow(const float *row, int ib, int ts, int lane, float (&v)[VEC], float &h) {
-    load_f32<VEC, false>(row + ib, v);
-    h = row[lane == kWave - 1 ? ts + kWave * VEC : ts - 1];
+__device__ __forceinline__ void issue_prow(const float *row, int il, int hl, int hr, int lane, float (&v)[VEC],
+                                           float &h) {
+    load_f32<VEC, false>(row + il, v);
+    h = row[lane == kWave - 1 ? hr : hl];
 }
 
 template <int VEC>
@@ -162,7 +163,13 @@ __device__ __forceinline__ void load_coefs(const GridView &g, long long off, flo
 }
 
 // Nest S for one wave: i-points ts + lane*VEC .. +VEC-1 of one line of the
-// grid, marching along it. Without OFL_TILE_MARCH_J the wave owns row j =
+// grid, marching along it. In packed-row form (a batched grid with
+// g.nseg > 0, k-march only) the line is a segment of 64*VEC consecutive
+// points of a plane that runs across row ends: `fixed` is 0, ts counts points
+// from the plane's start, and rows j-1, j+1 of a point lie one pitch before and
+// after it. The pitch is a multiple of 4, so a lane's VEC points share one
+// row. Points of row 0 that the first segment covers are never stored.
+// Without OFL_TILE_MARCH_J the wave owns row j =
 // `fixed` and marches through planes k = m0..m1-1 (consecutive steps one plane
 // apart); with it the wave owns plane k = `fixed` and marches through rows
 // j = m0..m1-1 (consecutive steps one row apart, so every stream the wave reads
@@ -178,10 +185,18 @@ __device__ __forceinline__ void sweep_march(const GridView &g, int ts, int fixed
     constexpr bool kMarchJ = (FLAGS & OFL_TILE_MARCH_J) != 0;
     const int lane = threadIdx.x & (kWave - 1);
     const int ib = ts + lane * VEC;
-    // Lanes whose vector starts past the row's last element load the row's
-    // last vector instead (same cache line, no extra HBM traffic); their
-    // results are never stored.
-    const int il = min(ib, ((g.I - 1) / VEC) * VEC);
+    const bool packed = !kMarchJ && g.nseg > 0;
+    const int flat_end = (g.J - 1) * g.pitch;  // packed: first point after row J-2
+    // Lanes whose vector starts past the row's last element (packed: past row
+    // J-2) load the last vector before that instead (same cache line, no extra
+    // HBM traffic); their results are never stored.
+    const int il = packed ? min(ib, flat_end - VEC) : min(ib, ((g.I - 1) / VEC) * VEC);
+    const int hl = ts - 1;
+    const int hr = packed ? min(ts + kWave * VEC, flat_end - 1) : ts + kWave * VEC;
+    // i of the lane's first point, and whether its row is an interior one
+    const int jr = packed ? ib / g.pitch : 0;
+    const int i0 = ib - jr * g.pitch;
+    const bool row_ok = !packed || (jr >= 1 && jr <= g.J - 2);
     const long long pitch = g.pitch;
     const long long plane = g.plane;
     const float *__restrict__ p = g.p;
@@ -202,9 +217,9 @@ __device__ __forceinline__ void sweep_march(const GridView &g, int ts, int fixed
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
                 if constexpr (kMarchJ)
-                    issue_prow<VEC>(row(m0 - 1 + a, fixed - 1 + b), il, ts, lane, P[a][b], h[a][b]);
+                    issue_prow<VEC>(row(m0 - 1 + a, fixed - 1 + b), il, hl, hr, lane, P[a][b], h[a][b]);
                 else
-                    issue_prow<VEC>(row(fixed - 1 + b, m0 - 1 + a), il, ts, lane, P[b][a], h[a][b]);
+                    issue_prow<VEC>(row(fixed - 1 + b, m0 - 1 + a), il, hl, hr, lane, P[b][a], h[a][b]);
             }
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -240,9 +255,9 @@ __device__ __forceinline__ void sweep_march(const GridView &g, int ts, int fixed
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
             if constexpr (kMarchJ)
-                issue_prow<VEC>(row(j + 1, k - 1 + b), il, ts, lane, P[2][b], h[b]);
+                issue_prow<VEC>(row(j + 1, k - 1 + b), il, hl, hr, lane, P[2][b], h[b]);
             else
-                issue_prow<VEC>(row(j - 1 + b, k + 1), il, ts, lane, P[b][2], h[b]);
+                issue_prow<VEC>(row(j - 1 + b, k + 1), il, hl, hr, lane, P[b][2], h[b]);
         }
         // Keep every load of the step ahead of the first use, so one wait
         // covers them all instead of the scheduler trading them for registers.
@@ -271,19 +286,19 @@ __device__ __forceinline__ void sweep_march(const GridView &g, int ts, int fixed
             out[e] = centre + omega * ss;
             if constexpr (kFuseR) {
                 // the residual nest's own term, (wrk2 - p) in FP32 squared in FP64
-                if (ib + e >= 1 && ib + e <= I - 2) {
+                if (row_ok && i0 + e >= 1 && i0 + e <= I - 2) {
                     const double d = static_cast<double>(out[e] - centre);
                     racc = fma(d, d, racc);
                 }
             }
         }
         float *w = wrk2 + j * pitch + k * plane + ib;
-        if (ib >= 1 && ib + VEC - 1 <= I - 2) {
+        if (row_ok && i0 >= 1 && i0 + VEC - 1 <= I - 2) {
             store_f32<VEC, kNtStores>(w, out);
         } else {
 #pragma unroll
             for (int e = 0; e < VEC; ++e)
-                if (ib + e >= 1 && ib + e <= I - 2)
+                if (row_ok && i0 + e >= 1 && i0 + e <= I - 2)
                     w[e] = out[e];
         }
 
@@ -381,6 +396,22 @@ __global__ __launch_bounds__(512) void batch_sweep_kernel(const GridView *__rest
         double *part = nullptr;
         if constexpr (kFuseR)
             part = parts + static_cast<long long>(w) * lines + wave;
+        if constexpr ((FLAGS & OFL_TILE_MARCH_J) == 0) {
+            if (g.nseg > 0) {
+                // packed rows: the work-group's waves own consecutive segments
+                const int seg = item.fblock * lines + wave;
+                if (seg >= g.nseg) {
+                    if constexpr (kFuseR)
+                        if ((threadIdx.x & (kWave - 1)) == 0)
+                            *part = 0.0;
+                    continue;
+                }
+                const int m0 = 1 + item.mchunk * chunk;
+                const int m1 = min(m0 + chunk, g.K - 1);
+                sweep_march<VEC, BF16, FLAGS>(g, packed_seg0(g.pitch) + seg * kWave * VEC, 0, m0, m1, omega, part);
+                continue;
+            }
+        }
         const int fixed = 1 + item.fblock * lines + wave;
         int fixed_last, march_end;
         march_extent<FLAGS>(g, fixed_last, march_end);
@@ -427,12 +458,25 @@ __device__ __forceinline__ double acc_value(const Acc &a) {
         return static_cast<double>(a.s) + static_cast<double>(a.c);
 }
 
-// Row tile rt of a grid -> offset of this lane's first element; false if the
-// tile index is past the end.
-// (ib receives the lane's first i; the returned offset addresses the lane's
-// load, clamped to the row's last vector like the sweep's loads.)
+// Row tile rt of a grid -> offset of this lane's load, clamped to the row's
+// last vector like the sweep's loads. i0 receives the i of the lane's first
+// point and ok whether its row is an interior one. Packed rows (g.nseg > 0):
+// tile rt is segment rt % nseg of plane 1 + rt / nseg, the same segments the
+// batched sweep uses.
 template <int VEC>
-__device__ __forceinline__ long long row_tile_offset(const GridView &g, int rt, int nti, int lane, int &ib) {
+__device__ __forceinline__ long long row_tile_offset(const GridView &g, int rt, int nti, int lane, int &i0,
+                                                     bool &ok) {
+    if (g.nseg > 0) {
+        const int seg = rt % g.nseg;
+        const int k = 1 + rt / g.nseg;
+        const int f = packed_seg0(g.pitch) + seg * kWave * VEC + lane * VEC;
+        const int jr = f / g.pitch;
+        i0 = f - jr * g.pitch;
+        ok = jr >= 1 && jr <= g.J - 2;
+        return k * g.plane + min(f, (g.J - 1) * g.pitch - VEC);
+    }
+    ok = true;
+    int &ib = i0;
     const int it = rt % nti;
     const int row = rt / nti;
     const int jj = g.J - 2;
@@ -455,9 +499,10 @@ __device__ __forceinline__ void residual_rows(const GridView &g, int first, int 
     for (int r0 = first; r0 <= last; r0 += kRowUnroll) {
         float pv[kRowUnroll][VEC], wv[kRowUnroll][VEC];
         int ib[kRowUnroll];
+        bool ok[kRowUnroll];
 #pragma unroll
         for (int u = 0; u < kRowUnroll; ++u) {
-            const long long off = row_tile_offset<VEC>(g, min(r0 + u, last), nti, lane, ib[u]);
+            const long long off = row_tile_offset<VEC>(g, min(r0 + u, last), nti, lane, ib[u], ok[u]);
             load_f32<VEC, NT>(g.p + off, pv[u]);
             load_f32<VEC, NT>(g.wrk2 + off, wv[u]);
         }
@@ -466,7 +511,7 @@ __device__ __forceinline__ void residual_rows(const GridView &g, int first, int 
             if (r0 + u <= last) {
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)
-                    if (ib[u] + e >= 1 && ib[u] + e <= I - 2)
+                    if (ok[u] && ib[u] + e >= 1 && ib[u] + e <= I - 2)
                         acc_add<SUM>(acc, wv[u][e] - pv[u][e]);
             }
     }
@@ -608,21 +653,22 @@ __device__ __forceinline__ void copyback_rows(const GridView &g, int first, int 
         float wv[kRowUnroll][VEC];
         long long off[kRowUnroll];
         int ib[kRowUnroll];
+        bool ok[kRowUnroll];
 #pragma unroll
         for (int u = 0; u < kRowUnroll; ++u) {
-            off[u] = row_tile_offset<VEC>(g, min(r0 + u, last), nti, lane, ib[u]);
+            off[u] = row_tile_offset<VEC>(g, min(r0 + u, last), nti, lane, ib[u], ok[u]);
             load_f32<VEC, NTL>(g.wrk2 + off[u], wv[u]);
         }
 #pragma unroll
         for (int u = 0; u < kRowUnroll; ++u) {
             if (r0 + u > last)
                 continue;
-            if (ib[u] >= 1 && ib[u] + VEC - 1 <= I - 2) {
+            if (ok[u] && ib[u] >= 1 && ib[u] + VEC - 1 <= I - 2) {
                 store_f32<VEC, NTS>(g.p + off[u], wv[u]);
             } else {
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)
-                    if (ib[u] + e >= 1 && ib[u] + e <= I - 2)
+                    if (ok[u] && ib[u] + e >= 1 && ib[u] + e <= I - 2)
                         g.p[off[u] + e] = wv[u][e];
             }
         }
@@ -655,27 +701,30 @@ __global__ __launch_bounds__(kResidualThreads) void batch_copyback_kernel(const 
 
 // -------------------------------------------------------- transfer helpers
 
-// Contiguous host-order staging buffer <-> pitched device array.
-template <typename T>
-__global__ void pack_kernel(const T *__restrict__ src, T *__restrict__ dst, int I, long long rows, int pitch) {
-    const long long n = rows * I;
-    for (long long t = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; t < n;
-         t += static_cast<long long>(gridDim.x) * blockDim.x) {
-        const long long row = t / I;
-        const int i = static_cast<int>(t - row * I);
-        dst[row * pitch + i] = src[t];
-    }
+// Contiguous host-order staging buffer <-> pitched device array. Host row
+// `row` is row row % J of plane row / J.
+__device__ __forceinline__ long long pitched_at(long long t, int I, int J, int pitch, long long plane) {
+    const long long row = t / I;
+    const int i = static_cast<int>(t - row * I);
+    const long long k = row / J;
+    const int j = static_cast<int>(row - k * J);
+    return k * plane + static_cast<long long>(j) * pitch + i;
 }
 
 template <typename T>
-__global__ void unpack_kernel(const T *__restrict__ src, T *__restrict__ dst, int I, long long rows, int pitch) {
-    const long long n = rows * I;
+__global__ void pack_kernel(const T *__restrict__ src, T *__restrict__ dst, int I, int J, long long n, int pitch,
+                            long long plane) {
     for (long long t = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; t < n;
-         t += static_cast<long long>(gridDim.x) * blockDim.x) {
-        const long long row = t / I;
-        const int i = static_cast<int>(t - row * I);
-        dst[t] = src[row * pitch + i];
-    }
+         t += static_cast<long long>(gridDim.x) * blockDim.x)
+        dst[pitched_at(t, I, J, pitch, plane)] = src[t];
+}
+
+template <typename T>
+__global__ void unpack_kernel(const T *__restrict__ src, T *__restrict__ dst, int I, int J, long long n, int pitch,
+                              long long plane) {
+    for (long long t = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; t < n;
+         t += static_cast<long long>(gridDim.x) * blockDim.x)
+        dst[t] = src[pitched_at(t, I, J, pitch, plane)];
 }
 
 __global__ void fill_zero_kernel(unsigned *__restrict__ dst, long long n) {
@@ -917,27 +966,29 @@ void launch_batch_copyback(const GridView *views, const RowItem *items, int nite
     check_launch("batched copy-back kernel launch");
 }
 
-void launch_pack(const void *staging, void *arr, int I, int J, int K, int pitch, int elem_bytes, hipStream_t s) {
-    const long long rows = static_cast<long long>(J) * K;
-    const int blocks = grid_for(rows * I, 256, 65536);
+void launch_pack(const void *staging, void *arr, int I, int J, int K, int pitch, long long plane, int elem_bytes,
+                 hipStream_t s) {
+    const long long n = static_cast<long long>(J) * K * I;
+    const int blocks = grid_for(n, 256, 65536);
     if (elem_bytes == 4)
-        pack_kernel<float><<<blocks, 256, 0, s>>>(static_cast<const float *>(staging), static_cast<float *>(arr), I,
-                                                 rows, pitch);
+        pack_kernel<float><<<blocks, 256, 0, s>>>(static_cast<const float *>(staging), static_cast<float *>(arr), I, J,
+                                                 n, pitch, plane);
     else
         pack_kernel<uint16_t><<<blocks, 256, 0, s>>>(static_cast<const uint16_t *>(staging),
-                                                    static_cast<uint16_t *>(arr), I, rows, pitch);
+                                                    static_cast<uint16_t *>(arr), I, J, n, pitch, plane);
     check_launch("pack kernel launch");
 }
 
-void launch_unpack(const void *arr, void *staging, int I, int J, int K, int pitch, int elem_bytes, hipStream_t s) {
-    const long long rows = static_cast<long long>(J) * K;
-    const int blocks = grid_for(rows * I, 256, 65536);
+void launch_unpack(const void *arr, void *staging, int I, int J, int K, int pitch, long long plane, int elem_bytes,
+                   hipStream_t s) {
+    const long long n = static_cast<long long>(J) * K * I;
+    const int blocks = grid_for(n, 256, 65536);
     if (elem_bytes == 4)
-        unpack_kernel<float><<<blocks, 256, 0, s>>>(static_cast<const float *>(arr), static_cast<float *>(staging),
-                                                   I, rows, pitch);
+        unpack_kernel<float><<<blocks, 256, 0, s>>>(static_cast<const float *>(arr), static_cast<float *>(staging), I,
+                                                   J, n, pitch, plane);
     else
         unpack_kernel<uint16_t><<<blocks, 256, 0, s>>>(static_cast<const uint16_t *>(arr),
-                                                      static_cast<uint16_t *>(staging), I, rows, pitch);
+                                                      static_cast<uint16_t *>(staging), I, J, n, pitch, plane);
     check_launch("unpack kernel launch");
 }
 

@@ -41,12 +41,13 @@ void hip_check(hipError_t e, const char *what);
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 // Device layout of one grid: every array pitched along i, rows 128-byte
-// aligned, with guard elements before and after so that whole-wave vector
-// loads that run past the last interior point stay inside the allocation.
+// aligned by default (or to row_align elements, a multiple of 4), with guard
+// elements before and after so that whole-wave vector loads that run past the
+// last interior point stay inside the allocation.
 struct Layout {
     int I = 0, J = 0, K = 0;
     int pitch = 0;          // elements per row
-    size_t plane = 0;       // pitch * J
+    size_t plane = 0;       // elements per plane: pitch * J (compact rows: padded to kSegAlign)
     size_t elems = 0;       // pitch * J * K
     size_t coef_elem = 4;   // bytes per stored coefficient (4 or 2)
     size_t off[OFL_NARRAYS] = {};  // byte offset of element 0 of each array in the block
@@ -56,7 +57,7 @@ struct Layout {
     size_t total = 0;       // bytes of the whole device block
 };
 
-Layout make_layout(int I, int J, int K, int coef_format);
+Layout make_layout(int I, int J, int K, int coef_format, int row_align = 0);
 
 // What a kernel needs to address one grid on the device.
 struct GridView {
@@ -65,6 +66,10 @@ struct GridView {
     const void *coef[kNCoef];  // float* (FP32) or uint16_t* (bfloat16 formats)
     float bias[kNCoef];
     int I, J, K, pitch;
+    // Batched grids only: > 0 when the grid runs in packed rows, as this many
+    // segments of 64 * VEC consecutive points per plane (rows 1..J-2), each
+    // wave's line running across row ends; 0 for the row-per-wave form.
+    int nseg;
     long long plane;
     double *partials;  // residual partial sums (batched: base of this grid's range)
     double *gosa;      // device scalar
@@ -90,6 +95,18 @@ ofl_tile to_tile(const TileCfg &c);
 
 __host__ __device__ inline int itiles(int I, int vec) { return (I - 2) / (kWave * vec) + 1; }
 
+// Packed rows (batched grids with short rows): a plane's rows 1..J-2 are cut
+// into segments of 64 * vec consecutive points, the first starting at the
+// last multiple of kSegAlign elements at or before row 1. With compact rows
+// planes are padded to kSegAlign elements, so every segment starts on a
+// 128-byte line in the FP32 arrays and in the bfloat16 ones.
+constexpr int kSegAlign = 64;
+__host__ __device__ inline int packed_seg0(int pitch) { return pitch / kSegAlign * kSegAlign; }
+__host__ __device__ inline long long packed_nseg(int J, int pitch, int vec) {
+    const long long span = static_cast<long long>(J - 1) * pitch - packed_seg0(pitch);
+    return (span + kWave * vec - 1) / (kWave * vec);
+}
+
 // Sweep decomposition of a grid: i-tiles, blocks of owned lines, march chunks.
 void sweep_shape(int I, int J, int K, const TileCfg &t, int *nti, int *nfb, int *nmc);
 
@@ -104,8 +121,10 @@ void launch_finalize(const double *partials, long long n, float omega, double *g
                      double *scratch = nullptr, int scratch_len = 0);
 void launch_residual(const GridView &g, int vec, int sum_mode, int flags, float omega, hipStream_t s);
 void launch_copyback(const GridView &g, int vec, int flags, hipStream_t s);
-void launch_pack(const void *staging, void *arr, int I, int J, int K, int pitch, int elem_bytes, hipStream_t s);
-void launch_unpack(const void *arr, void *staging, int I, int J, int K, int pitch, int elem_bytes, hipStream_t s);
+void launch_pack(const void *staging, void *arr, int I, int J, int K, int pitch, long long plane, int elem_bytes,
+                 hipStream_t s);
+void launch_unpack(const void *arr, void *staging, int I, int J, int K, int pitch, long long plane, int elem_bytes,
+                   hipStream_t s);
 void launch_fill_zero(void *ptr, size_t bytes, hipStream_t s);
 void launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 

@@ -463,6 +463,61 @@ def test_fused_batch_equals_unfused_batch(fusion, fmt):
         g.close()
 
 
+# Edge shapes for packed rows: the smallest grid, rows that fill whole
+# segments exactly ((J-2) * pitch a multiple of 256), one row, and a grid
+# whose rows are longer than a wave's segment.
+_PACKED_SIZES = [(3, 3, 3), (34, 66, 9), (5, 3, 7), (33, 33, 65), (300, 7, 6), (97, 41, 12), (62, 130, 5)]
+
+
+def _batch_run(probs, fmt, tile, row_align, iters, fusion=0):
+    grids = [ofl.Grid(a, coef_format=fmt, row_align=ra) for a, ra in zip(probs, row_align)]
+    b = ofl.ofl_batch_create([g.handle for g in grids], tile)
+    if fusion:
+        ofl.ofl_batch_set_fusion(b, fusion)
+    gosa = ofl.ofl_batch_run(b, iters, OMEGA, len(grids))
+    ofl.ofl_batch_destroy(b)
+    return grids, gosa
+
+
+@pytest.mark.parametrize("fusion", [0, ofl.OFL_FUSE_RESIDUAL | ofl.OFL_FUSE_COPYBACK_SWAP])
+@pytest.mark.parametrize("vec", [0, 2])
+@pytest.mark.parametrize("fmt", [ofl.OFL_COEF_F32, ofl.OFL_COEF_BF16_OFFSET])
+def test_packed_row_batch_equals_row_batch(fmt, vec, fusion):
+    say("packed-row batch fmt", fmt, "vec", vec, "fusion", fusion)
+    probs = [synth.make_problem(I, J, K, seed=synth.grid_seed(40 + t)) for t, (I, J, K) in enumerate(_PACKED_SIZES)]
+    tile = ofl.tile(vec=vec, rows=4, kchunk=4, flags=ofl.OFL_TILE_NT_LOADS)
+    ref, r_ref = _batch_run(probs, fmt, tile, [0] * len(probs), 5, fusion)
+    # compact rows everywhere but one grid, so both forms share the launches
+    aligns = [4, 4, 8, 4, 0, 16, 4]
+    grids, r = _batch_run(probs, fmt, tile, aligns, 5, fusion)
+    tol = TOL_P_F32 if fmt == ofl.OFL_COEF_F32 else TOL_BF16
+    tol_g = TOL_GOSA_F32 if fmt == ofl.OFL_COEF_F32 else TOL_BF16
+    for a, g, gr, x, xr in zip(probs, grids, ref, r, r_ref):
+        assert np.array_equal(g.p, gr.p)
+        assert x == pytest.approx(xr, rel=1e-12, abs=1e-300)
+        check_against_oracle(a, g, x, 5, tol_p=tol, tol_g=tol_g)
+    for g in grids + ref:
+        g.close()
+
+
+@pytest.mark.parametrize("row_align", [4, 8, 16])
+@pytest.mark.parametrize("tile", [dict(vec=1, rows=2, kchunk=3), dict(vec=4, rows=4, kchunk=4, flags=1),
+                                  dict(vec=2, rows=4, kchunk=5, flags=ofl.OFL_TILE_MARCH_J)], ids=str)
+def test_compact_rows_single_grid_bitwise(row_align, tile):
+    say("compact rows, single grid, align", row_align, tile)
+    a = synth.make_problem(45, 29, 23, seed=31)
+    ref = ofl.Grid(a)
+    g = ofl.Grid(a, row_align=row_align)
+    for h in (ref.handle, g.handle):
+        ofl.ofl_set_tile(h, ofl.tile(**tile))
+    x_ref = ofl.ofl_jacobi_run(ref.handle, 4, OMEGA)
+    x = ofl.ofl_jacobi_run(g.handle, 4, OMEGA)
+    assert np.array_equal(g.p, ref.p) and x == x_ref
+    check_against_oracle(a, g, x, 4)
+    ref.close()
+    g.close()
+
+
 def test_batch_graph_replays_continue_the_iteration():
     say("batch graph replay")
     probs = _small_batch(4)

@@ -71,6 +71,12 @@ def test_create_validates_arguments():
     assert "coefficient" in ofl.ofl_last_error()
     with pytest.raises(ofl.OflError):
         ofl.ofl_grid_device_bytes(3, 3, 2)
+    for bad in (1, 3, 6, 64, -4):
+        with pytest.raises(ofl.OflError) as e:
+            ofl.ofl_grid_create(_desc(a, row_align=bad))
+        assert e.value.code == ofl.OFL_EINVAL and "row_align" in ofl.ofl_last_error()
+    for good in (0, 4, 8, 16, 32):  # accepted; no device memory is taken at creation
+        ofl.ofl_grid_destroy(ofl.ofl_grid_create(_desc(a, row_align=good)))
 
 
 def test_run_validates_arguments():
