@@ -326,8 +326,11 @@ typedef struct ofl_batch ofl_batch;
  * batched kernels over a work list of tiles sorted largest grid first,
  * captured once into a HIP graph and launched as one graph. The grids keep
  * ownership of their arrays; the batch borrows them and must be destroyed
- * first. tile may be NULL (defaults). EINVAL for n < 1, NULL grids, mixed
- * devices or formats. */
+ * first. tile may be NULL: the vector width per grid (vec 0), 4 lines per
+ * work-group, 4-plane chunks, non-temporal loads and stores. A grid created
+ * with a compact desc.row_align whose rows fill few of a wave's lanes runs in
+ * packed rows: each wave covers 64 * vec consecutive points of a plane across
+ * row ends. EINVAL for n < 1, NULL grids, mixed devices or formats. */
 int ofl_batch_create(ofl_grid *const *grids, int n, const ofl_tile *tile, ofl_batch **out);
 void ofl_batch_destroy(ofl_batch *b);
 int ofl_batch_set_tile(ofl_batch *b, const ofl_tile *tile);

@@ -480,12 +480,13 @@ def _batch_run(probs, fmt, tile, row_align, iters, fusion=0):
 
 
 @pytest.mark.parametrize("fusion", [0, ofl.OFL_FUSE_RESIDUAL | ofl.OFL_FUSE_COPYBACK_SWAP])
-@pytest.mark.parametrize("vec", [0, 2])
+@pytest.mark.parametrize("vec,flags", [(0, ofl.OFL_TILE_NT_LOADS), (2, ofl.OFL_TILE_NT_LOADS),
+                                       (0, ofl.OFL_TILE_NT_LOADS | ofl.OFL_TILE_NT_STORES)])
 @pytest.mark.parametrize("fmt", [ofl.OFL_COEF_F32, ofl.OFL_COEF_BF16_OFFSET])
-def test_packed_row_batch_equals_row_batch(fmt, vec, fusion):
-    say("packed-row batch fmt", fmt, "vec", vec, "fusion", fusion)
+def test_packed_row_batch_equals_row_batch(fmt, vec, flags, fusion):
+    say("packed-row batch fmt", fmt, "vec", vec, "flags", flags, "fusion", fusion)
     probs = [synth.make_problem(I, J, K, seed=synth.grid_seed(40 + t)) for t, (I, J, K) in enumerate(_PACKED_SIZES)]
-    tile = ofl.tile(vec=vec, rows=4, kchunk=4, flags=ofl.OFL_TILE_NT_LOADS)
+    tile = ofl.tile(vec=vec, rows=4, kchunk=4, flags=flags)
     ref, r_ref = _batch_run(probs, fmt, tile, [0] * len(probs), 5, fusion)
     # compact rows everywhere but one grid, so both forms share the launches
     aligns = [4, 4, 8, 4, 0, 16, 4]
@@ -497,6 +498,17 @@ def test_packed_row_batch_equals_row_batch(fmt, vec, fusion):
         assert x == pytest.approx(xr, rel=1e-12, abs=1e-300)
         check_against_oracle(a, g, x, 5, tol_p=tol, tol_g=tol_g)
     for g in grids + ref:
+        g.close()
+
+
+def test_batch_default_tile():
+    say("batch default tile")
+    grids = [ofl.Grid(a, row_align=4) for a in _small_batch(2)]
+    b = ofl.ofl_batch_create([g.handle for g in grids])
+    assert ofl.ofl_batch_get_tile(b).as_dict() == dict(
+        vec=0, rows=4, kchunk=4, flags=ofl.OFL_TILE_NT_LOADS | ofl.OFL_TILE_NT_STORES, occupancy=0)
+    ofl.ofl_batch_destroy(b)
+    for g in grids:
         g.close()
 
 
