@@ -226,7 +226,7 @@ int ofl_grid_coef_bias(const ofl_grid *g, float bias[12]);
 
 /* ---- kernel tiles ------------------------------------------------------- */
 #define OFL_TILE_NT_LOADS 1   /* non-temporal loads of the coefficient streams */
-#define OFL_TILE_NT_STORES 2  /* non-temporal stores of wrk2 */
+#define OFL_TILE_NT_STORES 2  /* non-temporal stores of wrk2 (sweep) and p (copy-back) */
 #define OFL_TILE_PREFETCH 4   /* software-pipelined coefficient loads (next step during this one) */
 #define OFL_TILE_MARCH_J 8    /* waves march along j (own a k-plane) instead of along k (own a j-row) */
 #define OFL_TILE_XCD_REMAP 16 /* give each XCD one contiguous range of tiles (shared L2 for halos)

@@ -429,8 +429,10 @@ int ofl_batch_create(ofl_grid *const *grids, int n, const ofl_tile *tile, ofl_ba
             b->tile.vec = 0;
             b->tile.rows = 4;
             b->tile.kchunk = 4;
-            // Non-temporal wrk2 stores as well: measured on 64 uneven grids they
-            // add 6% to the plain batch and 7-18% to the fused one.
+            // Non-temporal stores as well: measured on 64 uneven grids they add 6%
+            // to the plain batch and 7-18% to the fused one. (Ordinary stores in
+            // the copy-back alone make it 1.6x faster, but the next sweep then
+            // writes the dirty lines of p back and loses as much.)
             b->tile.flags = OFL_TILE_NT_LOADS | OFL_TILE_NT_STORES;
             b->tile.occupancy = 0;
         }
