@@ -117,6 +117,9 @@ int batch_auto_vec(int I) {
 bool batch_packed(int I, int J, int pitch, const TileCfg &t, int *vec, int *nseg) {
     if (t.flags & OFL_TILE_MARCH_J)
         return false;
+    // The packed kernels count a plane's points in 32-bit ints.
+    if (static_cast<long long>(J) * pitch > 0x7fffffffLL - 4096)
+        return false;
     const int vrow = t.vec > 0 ? t.vec : batch_auto_vec(I);
     const int vpk = t.vec > 0 ? t.vec : 4;
     if (pitch % vpk != 0)

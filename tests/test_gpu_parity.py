@@ -152,6 +152,26 @@ def test_129x129x257_200_iterations():
     g.close()
 
 
+def test_full_batch_in_the_benchmark_configuration():
+    """The 64 uneven grids as the benchmark runs them: compact rows (packed
+    where that pays), the default batch tile, plain and fused; two iterations
+    against the oracle on every grid."""
+    say("64 uneven grids: generating")
+    probs = synth.make_batch(64)
+    say("64 uneven grids: oracle")
+    refs = [oracle.jacobi(a, 2, float(OMEGA)) for _, a in probs]
+    for fusion in (0, ofl.OFL_FUSE_RESIDUAL | ofl.OFL_FUSE_COPYBACK_SWAP):
+        say("64 uneven grids: batch, fusion", fusion)
+        grids = [ofl.Grid(a, row_align=4) for _, a in probs]
+        b = ofl.ofl_batch_create([g.handle for g in grids])
+        ofl.ofl_batch_set_fusion(b, fusion)
+        gosa = ofl.ofl_batch_run(b, 2, OMEGA, len(grids))
+        ofl.ofl_batch_destroy(b)
+        for (_, a), g, x, ref in zip(probs, grids, gosa, refs):
+            check_against_oracle(a, g, x, 2, ref=ref)
+            g.close()
+
+
 @pytest.fixture(scope="module")
 def headline():
     say("generating 257x257x513")
