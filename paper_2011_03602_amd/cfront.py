@@ -38,6 +38,7 @@ import os
 import re
 import subprocess
 import tempfile
+import threading
 from dataclasses import dataclass, field
 from typing import Dict, List, Optional, Tuple
 
@@ -89,6 +90,7 @@ class CProgram:
     local_arrays: Dict[str, List[str]]
     written: List[str]
     python: str
+    rtype: str = "float"
     program: Optional[fe.Program] = None
 
 
@@ -169,7 +171,7 @@ class _Parser:
         return text, idx
 
 
-def _parse_function(toks) -> Tuple[str, List[Param], list]:
+def _parse_function(toks) -> Tuple[str, str, List[Param], list]:
     p = _Parser(toks)
     kind, rtype, line = p.take()
     if rtype not in _TYPES:
@@ -193,7 +195,7 @@ def _parse_function(toks) -> Tuple[str, List[Param], list]:
     body = _block(p)
     if p.peek()[0] != "eof":
         raise FrontendError("C: only one function is read")
-    return name, params, body
+    return rtype, name, params, body
 
 
 def _block(p: _Parser) -> list:
@@ -320,9 +322,9 @@ def _lower(name: str, params: List[Param], body: list) -> Tuple[str, Dict[str, L
 
 def translate(source: str) -> CProgram:
     """Parse the C function and lower it (no analysis)."""
-    name, params, body = _parse_function(tokenize(source))
+    rtype, name, params, body = _parse_function(tokenize(source))
     py, local_arrays, written = _lower(name, params, body)
-    return CProgram(source, name, params, local_arrays, written, py)
+    return CProgram(source, name, params, local_arrays, written, py, rtype)
 
 
 def analyse(source: str) -> CProgram:
@@ -353,18 +355,12 @@ def offload(cp: CProgram, values: Dict[str, object], gene: int, **kw):
 
 def run_c(cp: CProgram, values: Dict[str, object], workdir: Optional[str] = None):
     """Compile the original C program with gcc and run it on the given numpy
-    arrays (FP32, updated in place) and scalars; returns its return value."""
-    d = workdir or tempfile.mkdtemp(prefix="ofl_c_")
-    src = os.path.join(d, "program.c")
-    lib = os.path.join(d, "libprogram.so")
-    with open(src, "w") as f:
-        f.write(cp.source)
-    subprocess.run(["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-o", lib, src], check=True,
-                   capture_output=True)
-    so = ctypes.CDLL(lib)
-    fn = getattr(so, cp.func)
+    arrays (FP32, updated in place) and scalars; returns its return value
+    (None for a void function). Every array must have the shape its declared
+    dimensions give. The call runs on a thread with a stack large enough for
+    the program's local arrays."""
     shape = next(np.asarray(values[q.name]).shape for q in cp.params if q.dims)
-    dim_vals = {}
+    dim_vals: Dict[str, int] = {}
     for q in cp.params:
         if q.dims:
             for dname, n in zip(q.dims, shape):
@@ -376,6 +372,9 @@ def run_c(cp: CProgram, values: Dict[str, object], workdir: Optional[str] = None
             a = values[q.name]
             if not (isinstance(a, np.ndarray) and a.dtype == np.float32 and a.flags.c_contiguous):
                 raise FrontendError(f"C: {q.name} must be a C-contiguous float32 array")
+            want = tuple(dim_vals.get(d) for d in q.dims)
+            if None in want or a.shape != want:
+                raise FrontendError(f"C: {q.name} has shape {a.shape}, its declaration asks for {q.dims}")
             argtypes.append(ctypes.c_void_p)
             args.append(a.ctypes.data)
         elif q.name in dim_vals:
@@ -387,6 +386,38 @@ def run_c(cp: CProgram, values: Dict[str, object], workdir: Optional[str] = None
         else:
             argtypes.append(ctypes.c_float if q.ctype == "float" else ctypes.c_double)
             args.append(float(values[q.name]))
+    local_bytes = sum(4 * int(np.prod([dim_vals.get(d, 0) for d in dims])) for dims in cp.local_arrays.values())
+
+    with tempfile.TemporaryDirectory(prefix="ofl_c_", dir=workdir) as d:
+        src = os.path.join(d, "program.c")
+        lib = os.path.join(d, "libprogram.so")
+        with open(src, "w") as f:
+            f.write(cp.source)
+        r = subprocess.run(["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-o", lib, src], capture_output=True,
+                           text=True)
+        if r.returncode != 0:
+            raise FrontendError(f"C: gcc failed: {r.stderr.strip()[:2000]}")
+        so = ctypes.CDLL(lib)
+    fn = getattr(so, cp.func)
     fn.argtypes = argtypes
-    fn.restype = ctypes.c_float
-    return fn(*args)
+    fn.restype = {"float": ctypes.c_float, "double": ctypes.c_double, "int": ctypes.c_int, "void": None}[cp.rtype]
+
+    out: Dict[str, object] = {}
+
+    def call():
+        try:
+            out["ret"] = fn(*args)
+        except BaseException as e:  # handed back to the caller's thread
+            out["error"] = e
+
+    old = threading.stack_size()
+    threading.stack_size(max(64 << 20, 2 * local_bytes + (16 << 20)))
+    try:
+        t = threading.Thread(target=call)
+        t.start()
+    finally:
+        threading.stack_size(old)
+    t.join()
+    if "error" in out:
+        raise out["error"]
+    return out["ret"]

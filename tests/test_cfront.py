@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import paper_2011_03602_amd as ofl
+import oracle
 import synth
 from helpers import OMEGA, TOL_GOSA_F32, TOL_P_F32, p_rel_err, rel_err
 from paper_2011_03602_amd import cfront as cf
@@ -59,6 +60,37 @@ def test_all_cpu_gene_matches_the_c_program(tmp_path):
     assert v is vals["v"]
     assert p_rel_err(v, want_vals["v"]) <= TOL_P_F32
     assert rel_err(res, res_c) <= TOL_GOSA_F32
+
+
+@needs_gcc
+def test_c_program_with_a_local_array_beyond_the_default_stack(tmp_path):
+    # tmp is a 10 MB variable-length array: more than a default 8 MB main-thread stack
+    arrays = synth.make_problem(160, 160, 100, seed=4)
+    want_vals = c_values(arrays, 1)
+    cp = cf.analyse(RELAX_C)
+    res_c = cf.run_c(cp, want_vals, str(tmp_path))
+    vals = c_values(arrays, 1)
+    res, v = cf.offload(cp, vals, gene=0)
+    assert p_rel_err(v, want_vals["v"]) <= TOL_P_F32
+    # the C program sums its residual in FP32 over 2.5M points; the library sums in FP64
+    _, g_ref = oracle.jacobi(arrays, 1, float(OMEGA))
+    assert rel_err(res, g_ref) <= TOL_GOSA_F32
+    assert rel_err(res_c, g_ref) <= 1e-2
+
+
+@needs_gcc
+def test_run_c_checks_shapes_and_reports_gcc_errors(tmp_path):
+    arrays = synth.make_problem(8, 7, 6, seed=3)
+    cp = cf.analyse(RELAX_C)
+    vals = c_values(arrays, 1)
+    vals["rhs"] = np.zeros((6, 7, 9), np.float32)
+    with pytest.raises(fe.FrontendError, match="rhs has shape"):
+        cf.run_c(cp, vals, str(tmp_path))
+    broken = cf.translate(RELAX_C)
+    broken.source = RELAX_C.replace("return res;", "return res")
+    with pytest.raises(fe.FrontendError, match="gcc failed"):
+        cf.run_c(broken, c_values(arrays, 1), str(tmp_path))
+    assert list(tmp_path.iterdir()) == []  # the build folder is removed
 
 
 def _variant(old, new):
