@@ -511,15 +511,144 @@ bool grid_whole_nests(const ofl_grid *g) {
     return true;
 }
 
+namespace {
+
+// ---- steady-state iterations from captured HIP graphs
+//
+// With every nest on the GPU as one region, hoisted transfers, no fusion, no
+// profiling events and no time limit, an iteration after the first is three
+// kernel launches (sweep, residual + its finalize, copy-back) and nothing
+// else: no transfer, no host work. Small grids are then bound by launch
+// overhead, so those iterations are captured once into a graph of up to
+// kGraphIters iterations and replayed. The capture records kernel launches
+// only (no memset or copy nodes). A graph is reused while the grid's view,
+// tile, omega and length are those it was captured with.
+constexpr int kGraphIters = 256;
+
+bool same_view(const GridView &a, const GridView &b) {
+    for (int n = 0; n < kNCoef; ++n)
+        if (a.coef[n] != b.coef[n] || a.bias[n] != b.bias[n])
+            return false;
+    return a.p == b.p && a.wrk2 == b.wrk2 && a.I == b.I && a.J == b.J && a.K == b.K && a.pitch == b.pitch &&
+           a.nseg == b.nseg && a.plane == b.plane && a.partials == b.partials && a.gosa == b.gosa;
+}
+
+bool same_tile(const TileCfg &a, const TileCfg &b) {
+    return a.vec == b.vec && a.rows == b.rows && a.kchunk == b.kchunk && a.flags == b.flags &&
+           a.occupancy == b.occupancy;
+}
+
+bool graph_eligible(const ofl_grid *g, int nests) {
+    return nests == 3 && g->mask == OFL_MASK_ALL_GPU && g->mode == OFL_XFER_HOISTED && g->fusion == 0 &&
+           !g->profiling && g->deadline_ns == 0 && grid_whole_nests(g);
+}
+
+void enqueue_iterations(ofl_grid *g, int iters, float omega) {
+    for (int it = 0; it < iters; ++it) {
+        launch_sweep(g->view, g->tile, g->fmt != OFL_COEF_F32, omega, g->stream);
+        launch_residual(g->view, g->tile.vec, g->sum_mode, g->tile.flags, omega, g->stream);
+        launch_copyback(g->view, g->tile.vec, g->tile.flags, g->stream);
+    }
+}
+
+// A graph of `iters` steady-state iterations, cached; nullptr when the stream
+// cannot be captured (for instance because the caller is capturing it).
+hipGraphExec_t loop_graph(ofl_grid *g, int iters, float omega) {
+    for (const auto &c : g->graphs)
+        if (c.exec && c.iters == iters && c.omega == omega && same_tile(c.tile, g->tile) && same_view(c.view, g->view))
+            return c.exec;
+    hipStreamCaptureStatus status = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(g->stream, &status) != hipSuccess || status != hipStreamCaptureStatusNone) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    auto &slot = g->graphs[g->graph_next];
+    g->graph_next ^= 1;
+    if (slot.exec) {
+        hip_check(hipGraphExecDestroy(slot.exec), "hipGraphExecDestroy");
+        slot.exec = nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    hip_check(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    try {
+        enqueue_iterations(g, iters, omega);
+    } catch (...) {
+        (void)hipStreamEndCapture(g->stream, &graph);
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        throw;
+    }
+    hip_check(hipStreamEndCapture(g->stream, &graph), "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    hip_check(e, "hipGraphInstantiate");
+    slot.exec = exec;
+    slot.view = g->view;
+    slot.tile = g->tile;
+    slot.omega = omega;
+    slot.iters = iters;
+    return exec;
+}
+
+// Iterations [from, iters) from graphs, if the planner moves nothing in them:
+// one iteration from the current state must plan no transfer and leave the
+// state as it was (then every later one does the same). Returns the number of
+// iterations run.
+int run_graphed(ofl_grid *g, int from, int iters, float omega) {
+    Validity v = g->valid;
+    std::vector<Xfer> xs;
+    for (int nest = 0; nest < 3; ++nest) {
+        plan_before(from, nest, true, g->mode, v, xs);
+        plan_after(from, nest, true, g->mode, v, xs);
+    }
+    if (!xs.empty() || std::memcmp(&v, &g->valid, sizeof v) != 0)
+        return 0;
+    int done = 0;
+    while (from + done < iters) {
+        const int n = std::min(iters - from - done, kGraphIters);
+        hipGraphExec_t exec = loop_graph(g, n, omega);
+        if (!exec)
+            break;
+        hip_check(hipGraphLaunch(exec, g->stream), "hipGraphLaunch");
+        done += n;
+    }
+    for (int nest = 0; nest < 3; ++nest) {
+        g->stats.gpu_nests[nest] += static_cast<uint64_t>(done);
+        g->stats.gpu_regions[nest] += static_cast<uint64_t>(done);
+    }
+    if (done > 0) {
+        g->gosa_on_dev = true;
+        g->pending = true;
+    }
+    return done;
+}
+
+}  // namespace
+
+void grid_drop_graphs(ofl_grid *g) {
+    for (auto &c : g->graphs)
+        if (c.exec) {
+            (void)hipGraphExecDestroy(c.exec);
+            c.exec = nullptr;
+        }
+}
+
 void grid_run_loop(ofl_grid *g, int iters, float omega, int nests) {
     if (nests == 3 && g->fusion != 0 && g->mask == OFL_MASK_ALL_GPU && g->mode == OFL_XFER_HOISTED &&
         g->batch_refs == 0 && grid_whole_nests(g)) {
         run_fused(g, iters, omega);
         return;
     }
+    const bool graphed = graph_eligible(g, nests) && iters > 1;
     std::vector<Xfer> xs;
     std::vector<int> ins;
     for (int it = 0; it < iters; ++it) {
+        if (graphed && it == 1) {
+            it += run_graphed(g, 1, iters, omega);
+            if (it >= iters)
+                break;
+        }
         for (int nest = 0; nest < nests; ++nest) {
             check_deadline(g);
             const bool gpu = ((g->mask >> nest) & 1u) != 0;
@@ -813,6 +942,7 @@ void ofl_grid_destroy(ofl_grid *g) {
             (void)hipFree(g->fused_parts);
         if (g->region_sums)
             (void)hipFree(g->region_sums);
+        grid_drop_graphs(g);
         if (g->own_block)
             (void)hipFree(g->block);
         if (g->own_stream)

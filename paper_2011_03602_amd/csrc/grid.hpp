@@ -72,6 +72,18 @@ struct ofl_grid {
     // A search stops a run that outlives its time limit (steady clock, ns; 0 = none).
     long long deadline_ns = 0;
 
+    // Steady-state iterations replayed from captured HIP graphs (whole nests,
+    // hoisted, every nest on the GPU): two cached graphs, one per length.
+    struct LoopGraph {
+        hipGraphExec_t exec = nullptr;
+        ofl::GridView view{};
+        ofl::TileCfg tile;
+        float omega = 0.f;
+        int iters = 0;
+    };
+    LoopGraph graphs[2];
+    int graph_next = 0;  // slot the next capture replaces
+
     bool broken = false;
     int batch_refs = 0;
 };

@@ -570,6 +570,54 @@ def test_batch_graph_replays_continue_the_iteration():
         g.close()
 
 
+# --------------------------------------------------------- graph replays
+
+
+@pytest.mark.parametrize("region", [True, False])
+@pytest.mark.parametrize("fmt", [ofl.OFL_COEF_F32, ofl.OFL_COEF_BF16_OFFSET])
+def test_graph_replays_equal_eager_runs(fmt, region):
+    """Whole-nest, hoisted, all-GPU runs replay their steady-state iterations
+    from captured graphs; with profiling on every nest is launched on its own.
+    Every call of the graphed grid must equal the eager grid's, through
+    replays of one graph, a second length, runs longer than one graph, single
+    iterations, a new tile and a new omega, with host copies and
+    synchronisations between the calls."""
+    say("graph replays, fmt", fmt, "region", region)
+    a = synth.make_problem(33, 33, 65, seed=71)
+    eager = ofl.Grid(a, coef_format=fmt)
+    graphed = ofl.Grid(a, coef_format=fmt)
+    ofl.ofl_set_profiling(eager.handle, True)
+    if region:
+        for g in (eager, graphed):
+            ofl.ofl_data_enter(g.handle)
+    total = 0
+    plan = [(7, OMEGA, None), (7, OMEGA, None), (3, OMEGA, None), (7, OMEGA, None), (300, OMEGA, None),
+            (1, OMEGA, None), (7, OMEGA, dict(vec=1, rows=2, kchunk=5, flags=1)), (7, OMEGA, None),
+            (5, np.float32(0.7), None), (7, OMEGA, None)]
+    for iters, om, tile in plan:
+        if tile:
+            for g in (eager, graphed):
+                ofl.ofl_set_tile(g.handle, ofl.tile(**tile))
+        x_e = ofl.ofl_jacobi_run(eager.handle, iters, om)
+        x_g = ofl.ofl_jacobi_run(graphed.handle, iters, om)
+        if region:
+            for g in (eager, graphed):
+                ofl.ofl_update_host(g.handle)
+        torch.cuda.synchronize()
+        assert np.array_equal(graphed.p, eager.p), (iters, om, tile)
+        assert x_g == x_e, (iters, om, tile)
+        total += iters
+    se, sg = ofl.ofl_get_stats(eager.handle), ofl.ofl_get_stats(graphed.handle)
+    assert list(sg.gpu_nests) == list(se.gpu_nests) == [total] * 3
+    assert list(sg.gpu_regions) == list(se.gpu_regions)
+    if region:
+        for g in (eager, graphed):
+            ofl.ofl_data_exit(g.handle)
+    assert np.array_equal(graphed.p, eager.p)
+    eager.close()
+    graphed.close()
+
+
 # -------------------------------------------------------------------- tuner
 
 
