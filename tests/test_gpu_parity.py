@@ -570,6 +570,26 @@ def test_batch_graph_replays_continue_the_iteration():
         g.close()
 
 
+def test_residual_sums_only_fresh_partials():
+    """The residual kernel's last block sums every block's partial. Iterations
+    at omega 0.1 alternate with ofl_residual (omega 1, partials 100x larger),
+    so a partial left over from the previous launch would be far off; every
+    value must agree with the library's CPU nests on the same iterates."""
+    say("residual partials, alternating scales")
+    a = synth.make_problem(67, 45, 37, seed=5)
+    gpu, cpu = ofl.Grid(a), ofl.Grid(a)
+    ofl.ofl_set_offload_mask(cpu.handle, ofl.OFL_MASK_ALL_CPU, ofl.OFL_XFER_HOISTED)
+    for step in range(6):
+        om = np.float32(0.1 if step % 2 else 1.3)
+        xg, xc = ofl.ofl_jacobi_run(gpu.handle, 1, om), ofl.ofl_jacobi_run(cpu.handle, 1, om)
+        assert rel_err(xg, xc) <= TOL_GOSA_F32, step
+        rg, rc = ofl.ofl_residual(gpu.handle), ofl.ofl_residual(cpu.handle)
+        assert rel_err(rg, rc) <= TOL_GOSA_F32, step
+        assert p_rel_err(gpu.p, cpu.p.astype(np.float64)) <= TOL_P_F32, step
+    gpu.close()
+    cpu.close()
+
+
 # --------------------------------------------------------- graph replays
 
 
