@@ -294,7 +294,7 @@ void batch_enqueue(ofl_batch *b, int iters, float omega) {
             for (int c = 0; c < 3; ++c)
                 if (b->r_cnt[c] > 0)
                     launch_batch_copyback(views, ritems + b->r_off[c], b->r_cnt[c], vecs[c], b->tile.flags,
-                                          blocks_for(b, b->r_cnt[c]), b->stream);
+                                          blocks_for(b, b->r_cnt[c]), b->stream, true);
     }
 }
 
@@ -305,8 +305,9 @@ void batch_prepare(ofl_batch *b) {
         std::vector<Xfer> xs;
         plan_enter(OFL_MASK_ALL_GPU, g->valid, xs);
         grid_exec(g, xs);
-        if (b->fusion & OFL_FUSE_COPYBACK_SWAP)
-            grid_sync_wrk2_boundary(g);
+        // wrk2 carries p's boundary: needed by the buffer exchange, and lets
+        // the copy-back write whole rows
+        grid_sync_wrk2_boundary(g);
         grid_sync(g);
     }
     batch_build_tables(b);

@@ -263,7 +263,7 @@ void gpu_nest(ofl_grid *g, int nest, float omega) {
         launch_residual(g->view, g->tile.vec, g->sum_mode, g->tile.flags, omega, g->stream);
         g->gosa_on_dev = true;
     } else {
-        launch_copyback(g->view, g->tile.vec, g->tile.flags, g->stream);
+        launch_copyback(g->view, g->tile.vec, g->tile.flags, g->stream, g->wrk2_boundary_ok);
     }
     prof_end(g);
     g->stats.gpu_nests[nest] += 1;
@@ -492,7 +492,7 @@ void run_fused(ofl_grid *g, int iters, float omega) {
             grid_swap_p_wrk2(g);
         } else {
             prof_begin(g, kC);
-            launch_copyback(g->view, g->tile.vec, g->tile.flags, g->stream);
+            launch_copyback(g->view, g->tile.vec, g->tile.flags, g->stream, g->wrk2_boundary_ok);
             prof_end(g);
         }
         plan_after(it, kC, true, OFL_XFER_HOISTED, g->valid, xs);
@@ -547,7 +547,7 @@ void enqueue_iterations(ofl_grid *g, int iters, float omega) {
     for (int it = 0; it < iters; ++it) {
         launch_sweep(g->view, g->tile, g->fmt != OFL_COEF_F32, omega, g->stream);
         launch_residual(g->view, g->tile.vec, g->sum_mode, g->tile.flags, omega, g->stream);
-        launch_copyback(g->view, g->tile.vec, g->tile.flags, g->stream);
+        launch_copyback(g->view, g->tile.vec, g->tile.flags, g->stream, g->wrk2_boundary_ok);
     }
 }
 
@@ -555,7 +555,8 @@ void enqueue_iterations(ofl_grid *g, int iters, float omega) {
 // cannot be captured (for instance because the caller is capturing it).
 hipGraphExec_t loop_graph(ofl_grid *g, int iters, float omega) {
     for (const auto &c : g->graphs)
-        if (c.exec && c.iters == iters && c.omega == omega && same_tile(c.tile, g->tile) && same_view(c.view, g->view))
+        if (c.exec && c.iters == iters && c.omega == omega && c.whole_rows == g->wrk2_boundary_ok &&
+            same_tile(c.tile, g->tile) && same_view(c.view, g->view))
             return c.exec;
     hipStreamCaptureStatus status = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(g->stream, &status) != hipSuccess || status != hipStreamCaptureStatusNone) {
@@ -588,6 +589,7 @@ hipGraphExec_t loop_graph(ofl_grid *g, int iters, float omega) {
     slot.tile = g->tile;
     slot.omega = omega;
     slot.iters = iters;
+    slot.whole_rows = g->wrk2_boundary_ok;
     return exec;
 }
 
@@ -640,10 +642,17 @@ void grid_run_loop(ofl_grid *g, int iters, float omega, int nests) {
         run_fused(g, iters, omega);
         return;
     }
+    // Every nest on the GPU as one region with hoisted transfers: after the
+    // first iteration's uploads, give the device wrk2 p's boundary once, so the
+    // copy-back writes whole rows from then on.
+    const bool resident = nests == 3 && g->mask == OFL_MASK_ALL_GPU && g->mode == OFL_XFER_HOISTED &&
+                          g->fusion == 0 && grid_whole_nests(g);
     const bool graphed = graph_eligible(g, nests) && iters > 1;
     std::vector<Xfer> xs;
     std::vector<int> ins;
     for (int it = 0; it < iters; ++it) {
+        if (resident && it == 1)
+            grid_sync_wrk2_boundary(g);
         if (graphed && it == 1) {
             it += run_graphed(g, 1, iters, omega);
             if (it >= iters)

@@ -80,6 +80,7 @@ struct ofl_grid {
         ofl::TileCfg tile;
         float omega = 0.f;
         int iters = 0;
+        bool whole_rows = false;
     };
     LoopGraph graphs[2];
     int graph_next = 0;  // slot the next capture replaces

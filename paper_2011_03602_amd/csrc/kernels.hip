@@ -459,13 +459,13 @@ __device__ __forceinline__ double acc_value(const Acc &a) {
 }
 
 // Row tile rt of a grid -> offset of this lane's load, clamped to the row's
-// last vector like the sweep's loads. i0 receives the i of the lane's first
-// point and ok whether its row is an interior one. Packed rows (g.nseg > 0):
-// tile rt is segment rt % nseg of plane 1 + rt / nseg, the same segments the
-// batched sweep uses.
+// last vector like the sweep's loads (whole_rows: to the padded row's last
+// vector). i0 receives the i of the lane's first point and ok whether its row
+// is an interior one. Packed rows (g.nseg > 0): tile rt is segment rt % nseg of
+// plane 1 + rt / nseg, the same segments the batched sweep uses.
 template <int VEC>
 __device__ __forceinline__ long long row_tile_offset(const GridView &g, int rt, int nti, int lane, int &i0,
-                                                     bool &ok) {
+                                                     bool &ok, bool whole_rows = false) {
     if (g.nseg > 0) {
         const int seg = rt % g.nseg;
         const int k = 1 + rt / g.nseg;
@@ -483,7 +483,7 @@ __device__ __forceinline__ long long row_tile_offset(const GridView &g, int rt, 
     const int j = 1 + row % jj;
     const int k = 1 + row / jj;
     ib = it * kWave * VEC + lane * VEC;
-    const int il = min(ib, ((g.I - 1) / VEC) * VEC);
+    const int il = min(ib, whole_rows ? g.pitch - VEC : ((g.I - 1) / VEC) * VEC);
     return j * static_cast<long long>(g.pitch) + k * g.plane + il;
 }
 
@@ -643,8 +643,12 @@ __global__ __launch_bounds__(kResidualThreads) void batch_finalize_parts_kernel(
 
 // ---------------------------------------------------------------- copy-back
 
+// whole_rows: the device wrk2 equals p outside the interior (boundary columns
+// and row padding), so every interior row is copied whole, boundary columns and
+// padding included. The result is the same, and every 128-byte line of those
+// rows is written in full instead of in part.
 template <int VEC, bool NTL, bool NTS>
-__device__ __forceinline__ void copyback_rows(const GridView &g, int first, int count) {
+__device__ __forceinline__ void copyback_rows(const GridView &g, int first, int count, bool whole_rows) {
     const int lane = threadIdx.x & (kWave - 1);
     const int nti = itiles(g.I, VEC);
     const int I = g.I;
@@ -656,14 +660,17 @@ __device__ __forceinline__ void copyback_rows(const GridView &g, int first, int 
         bool ok[kRowUnroll];
 #pragma unroll
         for (int u = 0; u < kRowUnroll; ++u) {
-            off[u] = row_tile_offset<VEC>(g, min(r0 + u, last), nti, lane, ib[u], ok[u]);
+            off[u] = row_tile_offset<VEC>(g, min(r0 + u, last), nti, lane, ib[u], ok[u], whole_rows);
             load_f32<VEC, NTL>(g.wrk2 + off[u], wv[u]);
         }
 #pragma unroll
         for (int u = 0; u < kRowUnroll; ++u) {
             if (r0 + u > last)
                 continue;
-            if (ok[u] && ib[u] >= 1 && ib[u] + VEC - 1 <= I - 2) {
+            if (whole_rows) {
+                if (ok[u] && ib[u] + VEC <= g.pitch)
+                    store_f32<VEC, NTS>(g.p + off[u], wv[u]);
+            } else if (ok[u] && ib[u] >= 1 && ib[u] + VEC - 1 <= I - 2) {
                 store_f32<VEC, NTS>(g.p + off[u], wv[u]);
             } else {
 #pragma unroll
@@ -676,17 +683,18 @@ __device__ __forceinline__ void copyback_rows(const GridView &g, int first, int 
 }
 
 template <int VEC, bool NTL, bool NTS>
-__global__ __launch_bounds__(kResidualThreads) void copyback_kernel(GridView g, int rows_per_wave, int nrt) {
+__global__ __launch_bounds__(kResidualThreads) void copyback_kernel(GridView g, int rows_per_wave, int nrt,
+                                                                    int whole_rows) {
     const int wave = blockIdx.x * (kResidualThreads / kWave) + static_cast<int>(threadIdx.x / kWave);
     const int first = wave * rows_per_wave;
     const int count = max(0, min(rows_per_wave, nrt - first));
-    copyback_rows<VEC, NTL, NTS>(g, first, count);
+    copyback_rows<VEC, NTL, NTS>(g, first, count, whole_rows != 0);
 }
 
 template <int VEC, bool NTL, bool NTS>
 __global__ __launch_bounds__(kResidualThreads) void batch_copyback_kernel(const GridView *__restrict__ views,
                                                                           const RowItem *__restrict__ items,
-                                                                          int nitems) {
+                                                                          int nitems, int whole_rows) {
     const int wave = static_cast<int>(threadIdx.x / kWave);
     constexpr int kWaves = kResidualThreads / kWave;
     for (int w = xcd_remap(blockIdx.x, gridDim.x); w < nitems; w += gridDim.x) {
@@ -695,7 +703,7 @@ __global__ __launch_bounds__(kResidualThreads) void batch_copyback_kernel(const 
         const int per = (item.count + kWaves - 1) / kWaves;
         const int first = item.first + wave * per;
         const int count = max(0, min(per, item.first + item.count - first));
-        copyback_rows<VEC, NTL, NTS>(g, first, count);
+        copyback_rows<VEC, NTL, NTS>(g, first, count, whole_rows != 0);
     }
 }
 
@@ -914,15 +922,16 @@ struct BatchResidualLaunch {
 // copy-back: the "sum mode" slot carries the non-temporal store choice
 template <int VEC, int NTS, bool NTL>
 struct CopybackLaunch {
-    static void run(dim3 grid, dim3 block, hipStream_t s, const GridView &g, int rpw, int nrt) {
-        copyback_kernel<VEC, NTL, NTS != 0><<<grid, block, 0, s>>>(g, rpw, nrt);
+    static void run(dim3 grid, dim3 block, hipStream_t s, const GridView &g, int rpw, int nrt, int whole_rows) {
+        copyback_kernel<VEC, NTL, NTS != 0><<<grid, block, 0, s>>>(g, rpw, nrt, whole_rows);
     }
 };
 
 template <int VEC, int NTS, bool NTL>
 struct BatchCopybackLaunch {
-    static void run(dim3 grid, dim3 block, hipStream_t s, const GridView *views, const RowItem *items, int n) {
-        batch_copyback_kernel<VEC, NTL, NTS != 0><<<grid, block, 0, s>>>(views, items, n);
+    static void run(dim3 grid, dim3 block, hipStream_t s, const GridView *views, const RowItem *items, int n,
+                    int whole_rows) {
+        batch_copyback_kernel<VEC, NTL, NTS != 0><<<grid, block, 0, s>>>(views, items, n, whole_rows);
     }
 };
 
@@ -938,12 +947,12 @@ void launch_residual(const GridView &g, int vec, int sum_mode, int flags, float 
     check_launch("residual finalize launch");
 }
 
-void launch_copyback(const GridView &g, int vec, int flags, hipStream_t s) {
+void launch_copyback(const GridView &g, int vec, int flags, hipStream_t s, bool whole_rows) {
     const int nrt = itiles(g.I, vec) * (g.J - 2) * (g.K - 2);
     const int blocks = grid_for(nrt, (kResidualThreads / kWave) * kRowUnroll * 2, kResidualBlocks * 4);
     const int rpw = rows_per_wave(nrt, blocks);
     by_vec_sum_nt<CopybackLaunch>(vec, (flags & OFL_TILE_NT_STORES) ? 1 : 0, (flags & OFL_TILE_NT_LOADS) != 0,
-                                  dim3(blocks), dim3(kResidualThreads), s, g, rpw, nrt);
+                                  dim3(blocks), dim3(kResidualThreads), s, g, rpw, nrt, whole_rows ? 1 : 0);
     check_launch("copy-back kernel launch");
 }
 
@@ -960,9 +969,10 @@ void launch_batch_finalize(const GridView *views, const int *partial_range, int 
 }
 
 void launch_batch_copyback(const GridView *views, const RowItem *items, int nitems, int vec, int flags,
-                           int grid_blocks, hipStream_t s) {
+                           int grid_blocks, hipStream_t s, bool whole_rows) {
     by_vec_sum_nt<BatchCopybackLaunch>(vec, (flags & OFL_TILE_NT_STORES) ? 1 : 0, (flags & OFL_TILE_NT_LOADS) != 0,
-                                       dim3(grid_blocks), dim3(kResidualThreads), s, views, items, nitems);
+                                       dim3(grid_blocks), dim3(kResidualThreads), s, views, items, nitems,
+                                       whole_rows ? 1 : 0);
     check_launch("batched copy-back kernel launch");
 }
 

@@ -120,7 +120,9 @@ long long sweep_waves(int I, int J, int K, const TileCfg &t);
 void launch_finalize(const double *partials, long long n, float omega, double *gosa, hipStream_t s,
                      double *scratch = nullptr, int scratch_len = 0);
 void launch_residual(const GridView &g, int vec, int sum_mode, int flags, float omega, hipStream_t s);
-void launch_copyback(const GridView &g, int vec, int flags, hipStream_t s);
+// whole_rows: the device wrk2 equals p outside the interior, so interior rows
+// are copied whole (same result, full-line writes).
+void launch_copyback(const GridView &g, int vec, int flags, hipStream_t s, bool whole_rows = false);
 void launch_pack(const void *staging, void *arr, int I, int J, int K, int pitch, long long plane, int elem_bytes,
                  hipStream_t s);
 void launch_unpack(const void *arr, void *staging, int I, int J, int K, int pitch, long long plane, int elem_bytes,
@@ -139,7 +141,7 @@ void launch_batch_residual(const GridView *views, const RowItem *items, int nite
 void launch_batch_finalize(const GridView *views, const int *partial_range, int ngrids, float omega,
                            hipStream_t s);
 void launch_batch_copyback(const GridView *views, const RowItem *items, int nitems, int vec, int flags,
-                           int grid_blocks, hipStream_t s);
+                           int grid_blocks, hipStream_t s, bool whole_rows);
 
 // Matrix product on the matrix cores (gemm.hip).
 void launch_gemm_f32(int M, int N, int K, const float *A, int lda, const float *B, int ldb, float *C, int ldc,

@@ -13,7 +13,7 @@ namespace {
 void launch_sweep(const GridView &, const TileCfg &, int, float, hipStream_t, double *) { no_device(); }
 void launch_finalize(const double *, long long, float, double *, hipStream_t, double *, int) { no_device(); }
 void launch_residual(const GridView &, int, int, int, float, hipStream_t) { no_device(); }
-void launch_copyback(const GridView &, int, int, hipStream_t) { no_device(); }
+void launch_copyback(const GridView &, int, int, hipStream_t, bool) { no_device(); }
 void launch_pack(const void *, void *, int, int, int, int, long long, int, hipStream_t) { no_device(); }
 void launch_unpack(const void *, void *, int, int, int, int, long long, int, hipStream_t) { no_device(); }
 void launch_fill_zero(void *, size_t, hipStream_t) { no_device(); }
@@ -27,7 +27,7 @@ void launch_batch_finalize_parts(const GridView *, const double *, const long lo
 }
 void launch_batch_residual(const GridView *, const RowItem *, int, int, int, int, int, hipStream_t) { no_device(); }
 void launch_batch_finalize(const GridView *, const int *, int, float, hipStream_t) { no_device(); }
-void launch_batch_copyback(const GridView *, const RowItem *, int, int, int, int, hipStream_t) { no_device(); }
+void launch_batch_copyback(const GridView *, const RowItem *, int, int, int, int, hipStream_t, bool) { no_device(); }
 void launch_gemm_f32(int, int, int, const float *, int, const float *, int, float *, int, hipStream_t) {
     no_device();
 }

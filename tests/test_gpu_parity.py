@@ -590,6 +590,31 @@ def test_residual_sums_only_fresh_partials():
     cpu.close()
 
 
+@pytest.mark.parametrize("row_align", [0, 4])
+def test_whole_row_copyback_keeps_the_boundary(row_align):
+    """After a resident run's first iteration the device wrk2 carries p's
+    boundary and the copy-back copies whole rows. Genes that move p or wrk2
+    between the host and the device in between must not let a stale boundary
+    through: every run is checked against the library's CPU nests, with the
+    boundary of p bitwise unchanged."""
+    say("whole-row copy-back, row_align", row_align)
+    a = synth.make_problem(45, 29, 23, seed=77)
+    gpu, cpu = ofl.Grid(a, row_align=row_align), ofl.Grid(a)
+    ofl.ofl_set_offload_mask(cpu.handle, ofl.OFL_MASK_ALL_CPU, ofl.OFL_XFER_HOISTED)
+    ofl.ofl_data_enter(gpu.handle)
+    for mask, mode in [(7, 1), (3, 1), (7, 1), (5, 0), (7, 1), (6, 1), (7, 0), (7, 1)]:
+        ofl.ofl_set_offload_mask(gpu.handle, mask, mode)
+        xg, xc = ofl.ofl_jacobi_run(gpu.handle, 3, OMEGA), ofl.ofl_jacobi_run(cpu.handle, 3, OMEGA)
+        ofl.ofl_update_host(gpu.handle)
+        assert boundary_equal(gpu.p, a["p"]), (mask, mode)
+        assert p_rel_err(gpu.p, cpu.p.astype(np.float64)) <= TOL_P_F32, (mask, mode)
+        assert rel_err(xg, xc) <= TOL_GOSA_F32, (mask, mode)
+    ofl.ofl_data_exit(gpu.handle)
+    assert boundary_equal(gpu.p, a["p"])
+    gpu.close()
+    cpu.close()
+
+
 # --------------------------------------------------------- graph replays
 
 
