@@ -292,14 +292,16 @@ __device__ __forceinline__ void sweep_march(const GridView &g, int ts, int fixed
                 }
             }
         }
-        float *w = wrk2 + j * pitch + k * plane + ib;
-        if (row_ok && i0 >= 1 && i0 + VEC - 1 <= I - 2) {
-            store_f32<VEC, kNtStores>(w, out);
-        } else {
+        // Points of an interior row outside the interior (its two boundary
+        // columns and the row padding) receive p's own value, so every lane that
+        // loaded its own points stores one whole vector and the rows of wrk2 are
+        // written in full 128-byte lines. The interior is what the nest computes.
+        if (row_ok && il == ib) {
 #pragma unroll
             for (int e = 0; e < VEC; ++e)
-                if (row_ok && i0 + e >= 1 && i0 + e <= I - 2)
-                    w[e] = out[e];
+                if (i0 + e < 1 || i0 + e > I - 2)
+                    out[e] = P[1][1][e];
+            store_f32<VEC, kNtStores>(wrk2 + j * pitch + k * plane + ib, out);
         }
 
         // slide the register window one step along the march axis
