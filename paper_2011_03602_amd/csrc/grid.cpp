@@ -443,8 +443,9 @@ namespace {
 // Fused iterations (gene 111, hoisted, fusion requested): the sweep also
 // produces the residual's per-wave partials (OFL_FUSE_RESIDUAL), and the
 // copy-back becomes a buffer exchange (OFL_FUSE_COPYBACK_SWAP), which is exact
-// because the sweep writes only the interior and wrk2's boundary was made
-// equal to p's first. The three nests still count as executed on the GPU.
+// because wrk2's boundary was made equal to p's first and the sweep writes
+// outside the interior only p's own values. The three nests still count as
+// executed on the GPU.
 void run_fused(ofl_grid *g, int iters, float omega) {
     grid_ensure_device(g);
     std::vector<Xfer> xs;
