@@ -10,15 +10,18 @@
 //
 //  * one wave owns one j-row and 64*VEC consecutive i-points (VEC per lane,
 //    loaded as one 4/8/16-byte vector), so every load and store is coalesced
-//    along the contiguous i axis;
+//    along the contiguous i axis; a batch runs a grid with short, compactly
+//    stored rows in packed form, where a wave's points run across row ends;
 //  * the wave marches through a chunk of k-planes keeping rows j-1, j, j+1 of
 //    planes k-1, k, k+1 in registers: each p value comes from memory once per
 //    row-march, the k+-1 neighbours never reload;
 //  * the i+-1 neighbours come from the adjacent lane through a cross-lane
 //    shuffle; only the two wave-edge lanes load one halo value each;
+//  * stores are whole vectors, so rows are written in full 128-byte lines;
 //  * no LDS and no barriers: the j+-1 rows are re-read by the waves of the
-//    neighbouring rows and served by L1/L2, and work-groups are remapped so
-//    that neighbouring j-blocks run on the same XCD (shared L2);
+//    neighbouring rows and served by L1/L2; work-groups go to the XCDs
+//    round-robin, so all of them stream the same window of HBM at once (an
+//    XCD-contiguous order is a tile option);
 //  * no MFMA: there is no dense contraction here.
 
 #include <algorithm>
