@@ -532,6 +532,26 @@ def test_batch_default_tile():
         g.close()
 
 
+@pytest.mark.parametrize("fmt", [ofl.OFL_COEF_F32, ofl.OFL_COEF_BF16_OFFSET])
+def test_packed_rows_on_random_shapes(fmt):
+    """16 seeded random shapes (I 3..300, J 3..80, K 3..40) with random compact
+    row alignments, as one packed batch, bitwise against the one-wave-per-row
+    batch on 128-byte rows."""
+    rng = np.random.default_rng(20110360)
+    shapes = [(int(rng.integers(3, 301)), int(rng.integers(3, 81)), int(rng.integers(3, 41))) for _ in range(16)]
+    aligns = [int(rng.choice([4, 8, 16])) for _ in shapes]
+    say("packed rows, random shapes", shapes, aligns)
+    probs = [synth.make_problem(I, J, K, seed=synth.grid_seed(100 + t)) for t, (I, J, K) in enumerate(shapes)]
+    tile = ofl.tile(vec=0, rows=4, kchunk=4, flags=ofl.OFL_TILE_NT_LOADS | ofl.OFL_TILE_NT_STORES)
+    ref, r_ref = _batch_run(probs, fmt, tile, [0] * len(probs), 3)
+    grids, r = _batch_run(probs, fmt, tile, aligns, 3)
+    for shape, g, gr, x, xr in zip(shapes, grids, ref, r, r_ref):
+        assert np.array_equal(g.p, gr.p), shape
+        assert x == pytest.approx(xr, rel=1e-12, abs=1e-300), shape
+    for g in grids + ref:
+        g.close()
+
+
 @pytest.mark.parametrize("row_align", [4, 8, 16])
 @pytest.mark.parametrize("tile", [dict(vec=1, rows=2, kchunk=3), dict(vec=4, rows=4, kchunk=4, flags=1),
                                   dict(vec=2, rows=4, kchunk=5, flags=ofl.OFL_TILE_MARCH_J)], ids=str)
