@@ -683,6 +683,47 @@ def test_graph_replays_equal_eager_runs(fmt, region):
     graphed.close()
 
 
+def test_separate_handles_run_concurrently():
+    """Separate handles may run at the same time from separate host threads on
+    their own streams (graph capture is thread-local). Four grids, two of them
+    with graph replay and two profiled (launched nest by nest), run
+    concurrently and must equal the same runs made one after another."""
+    import threading
+
+    say("concurrent handles")
+    probs = [synth.make_problem(40 + 7 * t, 33, 29 + t, seed=90 + t) for t in range(4)]
+
+    def run(a, profiled, out, slot):
+        g = ofl.Grid(a, torch_memory=True)
+        ofl.ofl_set_profiling(g.handle, profiled)
+        ofl.ofl_data_enter(g.handle)
+        xs = [ofl.ofl_jacobi_run(g.handle, 9, OMEGA) for _ in range(3)]
+        ofl.ofl_data_exit(g.handle)
+        out[slot] = (g.p.copy(), xs)
+        g.close()
+
+    seq = [None] * 4
+    for t, a in enumerate(probs):
+        run(a, t % 2 == 1, seq, t)
+    par = [None] * 4
+    errors = []
+
+    def guarded(t, a):
+        try:
+            run(a, t % 2 == 1, par, t)
+        except Exception as e:  # reported below, in the test's own thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=guarded, args=(t, a)) for t, a in enumerate(probs)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    assert not errors, errors
+    for (p_s, x_s), (p_p, x_p) in zip(seq, par):
+        assert np.array_equal(p_s, p_p) and x_s == x_p
+
+
 # -------------------------------------------------------------------- tuner
 
 
