@@ -255,15 +255,18 @@ void prof_end(ofl_grid *g) {
     g->prof_open = false;
 }
 
-void gpu_nest(ofl_grid *g, int nest, float omega) {
+// fold: the residual's finalize step runs inside the copy-back kernel that
+// follows it (both nests on the GPU as whole nests, hoisted transfers), which
+// saves one launch per iteration.
+void gpu_nest(ofl_grid *g, int nest, float omega, bool fold) {
     prof_begin(g, nest);
     if (nest == kS) {
         launch_sweep(g->view, g->tile, g->fmt != OFL_COEF_F32, omega, g->stream);
     } else if (nest == kR) {
-        launch_residual(g->view, g->tile.vec, g->sum_mode, g->tile.flags, omega, g->stream);
+        launch_residual(g->view, g->tile.vec, g->sum_mode, g->tile.flags, omega, g->stream, !fold);
         g->gosa_on_dev = true;
     } else {
-        launch_copyback(g->view, g->tile.vec, g->tile.flags, g->stream, g->wrk2_boundary_ok);
+        launch_copyback(g->view, g->tile.vec, g->tile.flags, g->stream, g->wrk2_boundary_ok, fold, omega);
     }
     prof_end(g);
     g->stats.gpu_nests[nest] += 1;
@@ -547,8 +550,8 @@ bool graph_eligible(const ofl_grid *g, int nests) {
 void enqueue_iterations(ofl_grid *g, int iters, float omega) {
     for (int it = 0; it < iters; ++it) {
         launch_sweep(g->view, g->tile, g->fmt != OFL_COEF_F32, omega, g->stream);
-        launch_residual(g->view, g->tile.vec, g->sum_mode, g->tile.flags, omega, g->stream);
-        launch_copyback(g->view, g->tile.vec, g->tile.flags, g->stream, g->wrk2_boundary_ok);
+        launch_residual(g->view, g->tile.vec, g->sum_mode, g->tile.flags, omega, g->stream, false);
+        launch_copyback(g->view, g->tile.vec, g->tile.flags, g->stream, g->wrk2_boundary_ok, true, omega);
     }
 }
 
@@ -649,6 +652,12 @@ void grid_run_loop(ofl_grid *g, int iters, float omega, int nests) {
     const bool resident = nests == 3 && g->mask == OFL_MASK_ALL_GPU && g->mode == OFL_XFER_HOISTED &&
                           g->fusion == 0 && grid_whole_nests(g);
     const bool graphed = graph_eligible(g, nests) && iters > 1;
+    // The residual's finalize step runs inside the copy-back kernel when both
+    // nests run on the GPU as whole nests with hoisted transfers (nothing reads
+    // gosa between them), and not under a search's time limit, which may stop
+    // a run between the two.
+    const bool fold = nests == 3 && (g->mask & 6u) == 6u && g->mode == OFL_XFER_HOISTED &&
+                      g->level[kR] == OFL_LEVEL_K && g->level[kC] == OFL_LEVEL_K && g->deadline_ns == 0;
     std::vector<Xfer> xs;
     std::vector<int> ins;
     for (int it = 0; it < iters; ++it) {
@@ -688,7 +697,7 @@ void grid_run_loop(ofl_grid *g, int iters, float omega, int nests) {
             }
             grid_exec(g, xs);
             if (gpu)
-                gpu_nest(g, nest, omega);
+                gpu_nest(g, nest, omega, fold && nest != kS);
             else
                 cpu_nest(g, nest, omega);
             xs.clear();

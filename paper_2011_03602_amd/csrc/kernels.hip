@@ -687,9 +687,14 @@ __device__ __forceinline__ void copyback_rows(const GridView &g, int first, int 
     }
 }
 
+// fin_n > 0: the residual nest ran just before as its own kernel and left
+// fin_n block partials; block 0 first turns them into gosa (the finalize step,
+// with the same fixed order), so that step needs no launch of its own.
 template <int VEC, bool NTL, bool NTS>
 __global__ __launch_bounds__(kResidualThreads) void copyback_kernel(GridView g, int rows_per_wave, int nrt,
-                                                                    int whole_rows) {
+                                                                    int whole_rows, int fin_n, double omega) {
+    if (fin_n > 0 && blockIdx.x == 0)
+        finalize_sum(g.partials, fin_n, omega, g.gosa);
     const int wave = blockIdx.x * (kResidualThreads / kWave) + static_cast<int>(threadIdx.x / kWave);
     const int first = wave * rows_per_wave;
     const int count = max(0, min(rows_per_wave, nrt - first));
@@ -927,8 +932,9 @@ struct BatchResidualLaunch {
 // copy-back: the "sum mode" slot carries the non-temporal store choice
 template <int VEC, int NTS, bool NTL>
 struct CopybackLaunch {
-    static void run(dim3 grid, dim3 block, hipStream_t s, const GridView &g, int rpw, int nrt, int whole_rows) {
-        copyback_kernel<VEC, NTL, NTS != 0><<<grid, block, 0, s>>>(g, rpw, nrt, whole_rows);
+    static void run(dim3 grid, dim3 block, hipStream_t s, const GridView &g, int rpw, int nrt, int whole_rows,
+                    int fin_n, double omega) {
+        copyback_kernel<VEC, NTL, NTS != 0><<<grid, block, 0, s>>>(g, rpw, nrt, whole_rows, fin_n, omega);
     }
 };
 
@@ -942,22 +948,26 @@ struct BatchCopybackLaunch {
 
 }  // namespace
 
-void launch_residual(const GridView &g, int vec, int sum_mode, int flags, float omega, hipStream_t s) {
+void launch_residual(const GridView &g, int vec, int sum_mode, int flags, float omega, hipStream_t s, bool finalize) {
     const int nrt = itiles(g.I, vec) * (g.J - 2) * (g.K - 2);
     const int rpw = rows_per_wave(nrt, kResidualBlocks);
     by_vec_sum_nt<ResidualLaunch>(vec, sum_mode, (flags & OFL_TILE_NT_LOADS) != 0, dim3(kResidualBlocks),
                                   dim3(kResidualThreads), s, g, rpw, nrt);
     check_launch("residual kernel launch");
+    if (!finalize)
+        return;
     finalize_kernel<<<1, kResidualThreads, 0, s>>>(g.partials, kResidualBlocks, static_cast<double>(omega), g.gosa);
     check_launch("residual finalize launch");
 }
 
-void launch_copyback(const GridView &g, int vec, int flags, hipStream_t s, bool whole_rows) {
+void launch_copyback(const GridView &g, int vec, int flags, hipStream_t s, bool whole_rows, bool finalize_residual,
+                     float omega) {
     const int nrt = itiles(g.I, vec) * (g.J - 2) * (g.K - 2);
     const int blocks = grid_for(nrt, (kResidualThreads / kWave) * kRowUnroll * 2, kResidualBlocks * 4);
     const int rpw = rows_per_wave(nrt, blocks);
     by_vec_sum_nt<CopybackLaunch>(vec, (flags & OFL_TILE_NT_STORES) ? 1 : 0, (flags & OFL_TILE_NT_LOADS) != 0,
-                                  dim3(blocks), dim3(kResidualThreads), s, g, rpw, nrt, whole_rows ? 1 : 0);
+                                  dim3(blocks), dim3(kResidualThreads), s, g, rpw, nrt, whole_rows ? 1 : 0,
+                                  finalize_residual ? kResidualBlocks : 0, static_cast<double>(omega));
     check_launch("copy-back kernel launch");
 }
 

@@ -119,10 +119,14 @@ long long sweep_waves(int I, int J, int K, const TileCfg &t);
 // least scratch_len doubles) large n is summed in two stages.
 void launch_finalize(const double *partials, long long n, float omega, double *gosa, hipStream_t s,
                      double *scratch = nullptr, int scratch_len = 0);
-void launch_residual(const GridView &g, int vec, int sum_mode, int flags, float omega, hipStream_t s);
+void launch_residual(const GridView &g, int vec, int sum_mode, int flags, float omega, hipStream_t s,
+                     bool finalize = true);
 // whole_rows: the device wrk2 equals p outside the interior, so interior rows
 // are copied whole (same result, full-line writes).
-void launch_copyback(const GridView &g, int vec, int flags, hipStream_t s, bool whole_rows = false);
+// finalize_residual: the residual kernel just ran without its finalize step
+// (launch_residual(..., false)); the copy-back's block 0 does it first.
+void launch_copyback(const GridView &g, int vec, int flags, hipStream_t s, bool whole_rows = false,
+                     bool finalize_residual = false, float omega = 1.f);
 void launch_pack(const void *staging, void *arr, int I, int J, int K, int pitch, long long plane, int elem_bytes,
                  hipStream_t s);
 void launch_unpack(const void *arr, void *staging, int I, int J, int K, int pitch, long long plane, int elem_bytes,
