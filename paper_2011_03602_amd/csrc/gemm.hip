@@ -5,7 +5,9 @@
 // C = A B for row-major FP32 matrices. A work-group of four waves owns a
 // 128 x 256 tile of C. Each wave owns a 64 x 128 quarter as 2 x 4 accumulator
 // tiles of 32 x 32, updated by v_mfma_f32_32x32x2_f32 (FP32 operands, FP32
-// accumulation); each operand value read from LDS feeds two or four products. The K dimension advances in stages of 16: the next stage's
+// accumulation); each operand value read from LDS feeds two or four products.
+// Products too small to give every CU two such tiles use 64 x 256 tiles (four
+// waves of 64 x 64 side by side), twice as many. The K dimension advances in stages of 16: the next stage's
 // A and B tiles are fetched from global memory into registers while the
 // current stage, held in LDS, feeds the matrix cores. LDS is double-buffered,
 // so one barrier per stage suffices.
@@ -29,8 +31,20 @@ namespace ofl {
 namespace {
 
 constexpr int kGemmThreads = 256;
-constexpr int kTileM = 128, kTileN = 256, kTileK = 16;
-constexpr int kNJ = kTileN / 64;                            // 32-wide accumulator tiles per wave along n
+constexpr int kTileN = 256, kTileK = 16;
+constexpr int kCus = 256;  // compute units of an MI355X
+
+// Work-group tile of TM x 256: four waves of 64 rows each, TM / 64 of them along
+// m and the rest along n; each thread fetches kAPer consecutive k of one A row.
+template <int TM>
+struct Shape {
+    static constexpr int kWavesM = TM / 64;
+    static constexpr int kWavesN = 4 / kWavesM;
+    static constexpr int kNJ = kTileN / kWavesN / 32;  // 32-wide accumulator tiles per wave along n
+    static constexpr int kAPer = TM * kTileK / kGemmThreads;
+    static constexpr int kAThreadsPerRow = kTileK / kAPer;
+    static_assert(kWavesM * kWavesN == kGemmThreads / 64 && kAPer % 4 == 0, "unsupported tile");
+};
 constexpr int kBThreadsPerRow = kTileN / 8;                 // threads loading one B row, 8 floats each
 constexpr int kBRowsPerPass = kGemmThreads / kBThreadsPerRow;
 constexpr int kBPasses = kTileK / kBRowsPerPass;            // passes over the B tile per stage
@@ -50,21 +64,25 @@ struct GemmArgs {
     int ldc;
 };
 
-// Fetch this thread's share of the A (128 x 16) and B (16 x 256) tiles at k0
-// into registers: A row tid / 2, columns (tid % 2) * 8 .. +8; B rows
-// pass * 8 + tid / 32, columns (tid % 32) * 8 .. +8, for pass 0 and 1.
-// Out-of-range elements read as zero. `vec`: the block's tiles lie inside the
-// matrices and every row start is 16-byte aligned, so whole float4 loads are
-// used.
+// Fetch this thread's share of the A (TM x 16) and B (16 x 256) tiles at k0
+// into registers: A row tid / kAThreadsPerRow, kAPer columns from
+// (tid % kAThreadsPerRow) * kAPer; B rows pass * 8 + tid / 32, columns
+// (tid % 32) * 8 .. +8, for pass 0 and 1. Out-of-range elements read as zero.
+// `vec`: the block's tiles lie inside the matrices and every row start is
+// 16-byte aligned, so whole float4 loads are used.
+template <int TM>
 __device__ __forceinline__ void fetch(const GemmArgs &g, int m0, int n0, int k0, bool vec, float *ra, float *rb) {
+    using S = Shape<TM>;
     const int tid = threadIdx.x;
-    const int am = m0 + (tid >> 1), ak = k0 + (tid & 1) * 8;
+    const int am = m0 + tid / S::kAThreadsPerRow, ak = k0 + (tid % S::kAThreadsPerRow) * S::kAPer;
     const int bn = n0 + (tid % kBThreadsPerRow) * 8;
     if (vec && k0 + kTileK <= g.K) {
         const float4 *pa = reinterpret_cast<const float4 *>(g.A + static_cast<size_t>(am) * g.lda + ak);
-        const float4 a0 = pa[0], a1 = pa[1];
-        ra[0] = a0.x; ra[1] = a0.y; ra[2] = a0.z; ra[3] = a0.w;
-        ra[4] = a1.x; ra[5] = a1.y; ra[6] = a1.z; ra[7] = a1.w;
+#pragma unroll
+        for (int q = 0; q < S::kAPer / 4; ++q) {
+            const float4 a = pa[q];
+            ra[4 * q] = a.x; ra[4 * q + 1] = a.y; ra[4 * q + 2] = a.z; ra[4 * q + 3] = a.w;
+        }
 #pragma unroll
         for (int pass = 0; pass < kBPasses; ++pass) {
             const int bk = k0 + pass * kBRowsPerPass + tid / kBThreadsPerRow;
@@ -77,7 +95,7 @@ __device__ __forceinline__ void fetch(const GemmArgs &g, int m0, int n0, int k0,
         return;
     }
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < S::kAPer; ++e) {
         const int k = ak + e;
         ra[e] = (am < g.M && k < g.K) ? g.A[static_cast<size_t>(am) * g.lda + k] : 0.f;
     }
@@ -92,15 +110,18 @@ __device__ __forceinline__ void fetch(const GemmArgs &g, int m0, int n0, int k0,
     }
 }
 
+template <int TM>
 __global__ __launch_bounds__(kGemmThreads) void gemm_f32_kernel(GemmArgs g, int vec_ok) {
+    using S = Shape<TM>;
+    constexpr int kNJ = S::kNJ;
     // A is kept transposed (k-major) so that a wave's operand fetch for one k
     // reads 32 consecutive floats.
-    __shared__ float As[2][kTileK][kTileM + kLdsPad];
+    __shared__ float As[2][kTileK][TM + kLdsPad];
     __shared__ float Bs[2][kTileK][kTileN + kLdsPad];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * (kTileN / 2);
+    const int wm = (wave / S::kWavesN) * 64, wn = (wave % S::kWavesN) * (kTileN / S::kWavesN);
     // Work-groups are dealt round-robin to the eight XCDs. Give each XCD a
     // contiguous run of tiles in row-major tile order instead, so that tiles
     // sharing rows of A (and neighbouring columns of B) meet in one XCD's L2.
@@ -112,8 +133,8 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_f32_kernel(GemmArgs g, int 
         by = t / gridDim.x;
         bx = t % gridDim.x;
     }
-    const int m0 = by * kTileM, n0 = bx * kTileN;
-    const bool vec = vec_ok && m0 + kTileM <= g.M && n0 + kTileN <= g.N;
+    const int m0 = by * TM, n0 = bx * kTileN;
+    const bool vec = vec_ok && m0 + TM <= g.M && n0 + kTileN <= g.N;
 
     floatx16 acc[2][kNJ];
 #pragma unroll
@@ -124,12 +145,12 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_f32_kernel(GemmArgs g, int 
             for (int r = 0; r < 16; ++r)
                 acc[i][j][r] = 0.f;
 
-    float ra[8], rb[8 * kBPasses];
+    float ra[S::kAPer], rb[8 * kBPasses];
     auto stash = [&](int buf) {
-        const int am = tid >> 1, ak = (tid & 1) * 8;
+        const int am = tid / S::kAThreadsPerRow, ak = (tid % S::kAThreadsPerRow) * S::kAPer;
         const int bn = (tid % kBThreadsPerRow) * 8;
 #pragma unroll
-        for (int e = 0; e < 8; ++e)
+        for (int e = 0; e < S::kAPer; ++e)
             As[buf][ak + e][am] = ra[e];
 #pragma unroll
         for (int pass = 0; pass < kBPasses; ++pass) {
@@ -140,7 +161,7 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_f32_kernel(GemmArgs g, int 
         }
     };
 
-    fetch(g, m0, n0, 0, vec, ra, rb);
+    fetch<TM>(g, m0, n0, 0, vec, ra, rb);
     stash(0);
     __syncthreads();
     const int lrow = lane >> 5, lcol = lane & 31;
@@ -148,7 +169,7 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_f32_kernel(GemmArgs g, int 
     for (int k0 = 0; k0 < g.K; k0 += kTileK) {
         const bool more = k0 + kTileK < g.K;
         if (more)
-            fetch(g, m0, n0, k0 + kTileK, vec, ra, rb);
+            fetch<TM>(g, m0, n0, k0 + kTileK, vec, ra, rb);
         // The operands of step kk + 2 are read from LDS before step kk's products
         // are issued (two register sets), so the LDS latency hides behind eight
         // matrix instructions; the scheduling barrier keeps the compiler from
@@ -205,8 +226,14 @@ void launch_gemm_f32(int M, int N, int K, const float *A, int lda, const float *
     const GemmArgs g{M, N, K, A, lda, B, ldb, C, ldc};
     const bool aligned = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (reinterpret_cast<uintptr_t>(B) % 16 == 0) &&
                          lda % 4 == 0 && ldb % 4 == 0;
-    const dim3 grid((N + kTileN - 1) / kTileN, (M + kTileM - 1) / kTileM);
-    hipLaunchKernelGGL(gemm_f32_kernel, grid, dim3(kGemmThreads), 0, s, g, aligned ? 1 : 0);
+    const long long tiles128 = static_cast<long long>((N + kTileN - 1) / kTileN) * ((M + 127) / 128);
+    if (tiles128 >= 2 * kCus) {
+        const dim3 grid((N + kTileN - 1) / kTileN, (M + 127) / 128);
+        hipLaunchKernelGGL(gemm_f32_kernel<128>, grid, dim3(kGemmThreads), 0, s, g, aligned ? 1 : 0);
+    } else {
+        const dim3 grid((N + kTileN - 1) / kTileN, (M + 63) / 64);
+        hipLaunchKernelGGL(gemm_f32_kernel<64>, grid, dim3(kGemmThreads), 0, s, g, aligned ? 1 : 0);
+    }
     hip_check(hipGetLastError(), "gemm kernel launch");
 }
 
