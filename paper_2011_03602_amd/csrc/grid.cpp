@@ -62,16 +62,9 @@ Layout make_layout(int I, int J, int K, int coef_format, int row_align) {
         off += (L.elems + kGuard) * eb;
         return at;
     };
-#ifndef OFL_ARRAY_STAGGER
-#define OFL_ARRAY_STAGGER 0
-#endif
-    for (int a = 0; a < kNCoef; ++a) {
-        off += static_cast<size_t>(OFL_ARRAY_STAGGER) * a;
+    for (int a = 0; a < kNCoef; ++a)
         L.off[a] = place(L.coef_elem);
-    }
-    off += static_cast<size_t>(OFL_ARRAY_STAGGER) * 12;
     L.off[OFL_ARR_P] = place(4);
-    off += static_cast<size_t>(OFL_ARRAY_STAGGER) * 13;
     L.off[OFL_ARR_WRK2] = place(4);
     L.staging_off = align_up(off, 256);
     off = L.staging_off + static_cast<size_t>(I) * J * K * 4;

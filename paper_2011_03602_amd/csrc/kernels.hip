@@ -143,13 +143,8 @@ __device__ __forceinline__ void issue_prow(const float *row, int il, int hl, int
 
 template <int VEC>
 __device__ __forceinline__ void finish_prow(const float (&v)[VEC], float h, int lane, float &l, float &r) {
-#ifdef OFL_USE_DPP
-    const float up = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[VEC - 1]), 0x138, 0xf, 0xf, false));
-    const float dn = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[0]), 0x130, 0xf, 0xf, false));
-#else
     const float up = __shfl_up(v[VEC - 1], 1, kWave);
     const float dn = __shfl_down(v[0], 1, kWave);
-#endif
     l = (lane == 0) ? h : up;
     r = (lane == kWave - 1) ? h : dn;
 }
