@@ -166,7 +166,45 @@ int main(void) {
     d.coef[4] = pb.arr[4];
     d.coef_format = 9;
     CHECK(ofl_grid_create(&d, &g) == OFL_EINVAL);
+    d.coef_format = 0;
+    {
+        /* compact rows: valid alignments create a handle, others are refused */
+        static const int bad[] = {1, 2, 3, 5, 12, 64, -4};
+        for (unsigned t = 0; t < sizeof bad / sizeof bad[0]; ++t) {
+            d.row_align = bad[t];
+            CHECK(ofl_grid_create(&d, &g) == OFL_EINVAL && strstr(ofl_last_error(), "row_align") != NULL);
+        }
+        static const int good[] = {0, 4, 8, 16, 32};
+        for (unsigned t = 0; t < sizeof good / sizeof good[0]; ++t) {
+            d.row_align = good[t];
+            CHECK(ofl_grid_create(&d, &g) == OFL_OK && g);
+            ofl_grid_destroy(g);
+            g = NULL;
+        }
+        d.row_align = 0;
+    }
     drop(&pb);
+    {
+        /* an all-CPU run does not depend on the row alignment */
+        problem pa, pc;
+        make(&pa, 13, 9, 7);
+        make(&pc, 13, 9, 7);
+        for (int a = 0; a < 14; ++a) /* the same problem twice */
+            memcpy(pc.arr[a], pa.arr[a], sizeof(float) * 13 * 9 * 7);
+        ofl_grid_desc da = desc_of(&pa, 0, 0), dc = desc_of(&pc, 0, 0);
+        dc.row_align = 4;
+        ofl_grid *ga = NULL, *gc = NULL;
+        CHECK(ofl_grid_create(&da, &ga) == OFL_OK && ofl_grid_create(&dc, &gc) == OFL_OK);
+        CHECK(ofl_set_offload_mask(ga, OFL_MASK_ALL_CPU, OFL_XFER_HOISTED) == OFL_OK);
+        CHECK(ofl_set_offload_mask(gc, OFL_MASK_ALL_CPU, OFL_XFER_HOISTED) == OFL_OK);
+        double xa = 0, xc = 1;
+        CHECK(ofl_jacobi_run(ga, 3, 0.8f, &xa) == OFL_OK && ofl_jacobi_run(gc, 3, 0.8f, &xc) == OFL_OK && xa == xc);
+        CHECK(memcmp(pa.arr[12], pc.arr[12], sizeof(float) * 13 * 9 * 7) == 0);
+        ofl_grid_destroy(ga);
+        ofl_grid_destroy(gc);
+        drop(&pa);
+        drop(&pc);
+    }
     size_t bytes = 0;
     CHECK(ofl_grid_device_bytes(257, 257, 513, OFL_COEF_F32, &bytes) == OFL_OK && bytes > 14ull * 257 * 257 * 513 * 4);
     CHECK(ofl_grid_device_bytes(2, 3, 3, OFL_COEF_F32, &bytes) == OFL_EINVAL);
