@@ -7,12 +7,14 @@ the inputs already resident in HBM (a data region is open before timing).
 value = lattice updates per second of the whole iteration, in GLUP/s.
 
 Also reported: the sweep kernel against the HBM roofline (HIP-event time of
-every sweep launch inside the timed region), the bfloat16-offset and batched
-forms of the same metric, and the FP64 oracle timed on a bounded sample on the
+every sweep launch inside the timed region, and the counter-measured bytes when
+they were taken on the current kernel source), the streaming ceiling of a 1 GiB
+copy, the bfloat16-offset, fused and batched forms of the same metric (batches
+with GA-tuned tiles), and the FP64 oracle timed on a bounded sample on the
 host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-variants]
-       [--skip-cpu-baseline] [--profile-only NAME]
+       [--skip-cpu-baseline] [--no-tune-batch] [--profile-only NAME]
        [--config headline|masks|precision|loops|blocks]
 """
 
@@ -504,6 +506,41 @@ def cpu_program(ofl, arrays, iters):
             "sample": f"257x257x513 grid, {iters} iterations, FP32, {dt:.2f} s"}
 
 
+def host_info():
+    """The host the CPU baselines ran on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "cpus_available": len(os.sched_getaffinity(0))}
+
+
+def copy_ceiling(ofl, reps=5):
+    """The library's copy kernel on 1 GiB: the streaming ceiling of a read + write pattern (GB/s moved)."""
+    import torch
+
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    s = torch.cuda.current_stream()
+    ofl.ofl_device_copy(dst.data_ptr(), src.data_ptr(), nbytes, s.cuda_stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        ofl.ofl_device_copy(dst.data_ptr(), src.data_ptr(), nbytes, s.cuda_stream)
+    e1.record(s)
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return {"kernel": "copy_kernel, 1 GiB read + 1 GiB written", "gbs": round(gbs, 1),
+            "frac": round(gbs / PEAK_HBM_GBS, 4)}
+
+
 def cpu_baseline(arrays, iters):
     import oracle
 
@@ -519,6 +556,7 @@ def cpu_baseline(arrays, iters):
         "kind": "oracle",
         "sample": f"257x257x513 grid, {iters} of the {ITERS} iterations, plain C FP64 oracle, one thread, "
                   f"{dt:.1f} s including the FP32->FP64 widening of the inputs",
+        "host": host_info(),
     }
 
 
@@ -531,7 +569,9 @@ def main():
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--batch-grids", type=int, default=64)
-    ap.add_argument("--tune-batch", action="store_true", help="run the GA tile search before the batched run")
+    ap.add_argument("--tune-batch", action=argparse.BooleanOptionalAction, default=True,
+                    help="run the GA tile search before each batched run (default; --no-tune-batch keeps the default "
+                         "batch tile)")
     ap.add_argument("--batch-row-align", type=int, default=4,
                     help="device row alignment of the batched grids (4: packed rows; 0: 128-byte rows)")
     ap.add_argument("--tune", action="store_true",
@@ -621,6 +661,8 @@ def main():
         "unit": "GB/s",
         "frac": round(achieved / PEAK_HBM_GBS, 4),
         "traffic": traffic,
+        "counter_gbs": round(traffic / (sweep_us * 1e-6) / 1e9, 1) if traffic else None,
+        "counter_frac": round(traffic / (sweep_us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4) if traffic else None,
         "avg_launch_us": round(sweep_us, 2),
         "timed_launches": head["nest_launches"][0],
         "algorithmic_bytes_per_launch": SWEEP_BYTES["f32"] * lup_launch,
@@ -654,6 +696,7 @@ def main():
         },
         "hbm_gbs_iteration": round(head["glups"] * ITER_BYTES["f32"], 1),
         "roofline": roofline,
+        "stream_copy_ceiling": copy_ceiling(ofl),
     }
     if not args.skip_variants:
         log("bf16-offset variant")
