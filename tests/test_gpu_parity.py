@@ -187,6 +187,27 @@ def test_257x257x513_first_iterations(headline):
     g.close()
 
 
+@pytest.mark.parametrize("form", ["bf16_offset", "fused_f32", "fused_bf16_offset"])
+def test_257x257x513_variants_first_iterations(headline, form):
+    """The benchmark's other single-grid forms at full size, in its launch
+    configuration (default tile, PyTorch arena and stream, inside a data
+    region): two iterations against the oracle on the FP32 inputs."""
+    say("257x257x513 x2", form)
+    a = headline
+    fmt = ofl.OFL_COEF_BF16_OFFSET if "bf16" in form else ofl.OFL_COEF_F32
+    g = ofl.Grid(a, coef_format=fmt, torch_memory=True)
+    if form.startswith("fused"):
+        ofl.ofl_set_fusion(g.handle, ofl.OFL_FUSE_RESIDUAL | ofl.OFL_FUSE_COPYBACK_SWAP)
+    ofl.ofl_data_enter(g.handle)
+    gosa = ofl.ofl_jacobi_run(g.handle, 2, OMEGA)
+    ofl.ofl_data_exit(g.handle)
+    tol = TOL_BF16 if fmt != ofl.OFL_COEF_F32 else TOL_P_F32
+    tol_g = TOL_BF16 if fmt != ofl.OFL_COEF_F32 else TOL_GOSA_F32
+    pe, ge = check_against_oracle(a, g, gosa, 2, tol_p=tol, tol_g=tol_g)
+    say(f"  p rel {pe:.2e} gosa rel {ge:.2e}")
+    g.close()
+
+
 def test_257x257x513_100th_iteration(headline):
     """The 100-iteration run in the benchmark's configuration: after 99
     iterations inside a data region, fetch p; the 100th step must equal one
