@@ -225,7 +225,10 @@ int ofl_set_fusion(ofl_grid *g, unsigned flags);
 int ofl_grid_coef_bias(const ofl_grid *g, float bias[12]);
 
 /* ---- kernel tiles ------------------------------------------------------- */
-#define OFL_TILE_NT_LOADS 1   /* non-temporal loads of the coefficient streams */
+#define OFL_TILE_NT_LOADS 1   /* non-temporal loads of the coefficient streams (sweep), of wrk2
+                                 (copy-back) and of a batch residual's inputs; a single grid's
+                                 residual always loads ordinarily, leaving p and wrk2 cached
+                                 for the copy-back that follows */
 #define OFL_TILE_NT_STORES 2  /* non-temporal stores of wrk2 (sweep) and p (copy-back) */
 #define OFL_TILE_PREFETCH 4   /* software-pipelined coefficient loads (next step during this one) */
 #define OFL_TILE_MARCH_J 8    /* waves march along j (own a k-plane) instead of along k (own a j-row) */
