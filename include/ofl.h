@@ -232,8 +232,11 @@ int ofl_grid_coef_bias(const ofl_grid *g, float bias[12]);
 #define OFL_TILE_NT_STORES 2  /* non-temporal stores of wrk2 (sweep) and p (copy-back) */
 #define OFL_TILE_PREFETCH 4   /* software-pipelined coefficient loads (next step during this one) */
 #define OFL_TILE_MARCH_J 8    /* waves march along j (own a k-plane) instead of along k (own a j-row) */
-#define OFL_TILE_XCD_REMAP 16 /* give each XCD one contiguous range of tiles (shared L2 for halos)
-                                 instead of round-robin (all XCDs stream one window of HBM) */
+#define OFL_TILE_XCD_REMAP 16 /* give each XCD one contiguous range of the sweep's tiles over the
+                                 whole grid; by default each XCD takes one contiguous band of
+                                 every k-chunk's tiles (when a k-chunk holds a multiple of 8;
+                                 else tiles go round-robin), so all XCDs stream one window of
+                                 HBM while j-neighbours share an L2 */
 
 typedef struct ofl_tile {
     int vec;       /* consecutive i-points per lane: 1, 2 or 4 (a wave spans 64*vec points);

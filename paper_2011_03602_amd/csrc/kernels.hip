@@ -19,9 +19,10 @@
 //    shuffle; only the two wave-edge lanes load one halo value each;
 //  * stores are whole vectors, so rows are written in full 128-byte lines;
 //  * no LDS and no barriers: the j+-1 rows are re-read by the waves of the
-//    neighbouring rows and served by L1/L2; work-groups go to the XCDs
-//    round-robin, so all of them stream the same window of HBM at once (an
-//    XCD-contiguous order is a tile option);
+//    neighbouring rows and served by L1/L2; every XCD takes one contiguous
+//    band of row blocks from each k-chunk, so neighbouring blocks share an L2
+//    while all XCDs stream the same window of HBM at once (an XCD-contiguous
+//    order over the whole grid is a tile option);
 //  * no MFMA: there is no dense contraction here.
 
 #include <algorithm>
@@ -54,6 +55,24 @@ __device__ __forceinline__ int xcd_remap(int bid, int n) {
     const int rem = n % kXcds;
     return xcd * per + min(xcd, rem) + local;
 }
+
+// The sweep's default order when a k-chunk holds a multiple of 8 tiles (`row`
+// of them, k-chunk slowest): XCD x takes tiles [x*row/8, (x+1)*row/8) of every
+// k-chunk, k-chunk after k-chunk. All XCDs still work on the same k-chunks at
+// once, and a block's j-neighbours run beside it on the same XCD, so the halo
+// rows they share are fetched into one L2 once instead of into two. Measured at
+// 257x257x513: fetched bytes per sweep 1.871 -> 1.776 GB (FP32) and
+// 1.115 -> 1.006 GB (bfloat16), the sweep 320.2 -> 319.5 us and 196.2 -> 194.6 us.
+__device__ __forceinline__ int xcd_band(int bid, int row) {
+    const int xcd = bid % kXcds;
+    const int slot = bid / kXcds;
+    const int per = row / kXcds;
+    return (slot / per) * row + xcd * per + slot % per;
+}
+
+// Order of a sweep launch's tiles: round-robin by block id, XCD-contiguous
+// ranges (OFL_TILE_XCD_REMAP), or XCD bands of each k-chunk.
+enum : int { kOrderPlain = 0, kOrderRemap = 1, kOrderBand = 2 };
 
 template <bool NT, typename T>
 __device__ __forceinline__ T ld(const T *ptr) {
@@ -355,8 +374,11 @@ __device__ __forceinline__ void march_extent(const GridView &g, int &fixed_last,
 
 template <int VEC, bool BF16, int FLAGS>
 __global__ __launch_bounds__(512) void sweep_kernel(GridView g, int chunk, int nti, int nfb, float omega,
-                                                    int remap, double *parts) {
-    const int L = remap ? xcd_remap(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x);
+                                                    int order, double *parts) {
+    const int bid = static_cast<int>(blockIdx.x);
+    const int L = order == kOrderBand    ? xcd_band(bid, nti * nfb)
+                  : order == kOrderRemap ? xcd_remap(bid, gridDim.x)
+                                         : bid;
     // fused residual: one partial per wave of the launch, every slot written
     double *part = nullptr;
     if constexpr ((FLAGS & kFlagFuseResidual) != 0)
@@ -789,8 +811,11 @@ using BatchSweepLaunch = void (*)(const GridView *, const SweepItem *, int, cons
 template <int VEC, bool BF16, int FLAGS>
 void sweep_one(const GridView &g, const TileCfg &t, float omega, int nti, int nfb, int blocks, double *parts,
                hipStream_t s) {
-    sweep_kernel<VEC, BF16, FLAGS><<<blocks, kWave * t.rows, 0, s>>>(g, t.kchunk, nti, nfb, omega,
-                                                                      (t.flags & OFL_TILE_XCD_REMAP) ? 1 : 0, parts);
+    // bands need whole k-chunks of a multiple of 8 tiles (blocks = nti*nfb*nmc)
+    const int order = (t.flags & OFL_TILE_XCD_REMAP) ? kOrderRemap
+                      : ((nti * nfb) % kXcds == 0) ? kOrderBand
+                                                   : kOrderPlain;
+    sweep_kernel<VEC, BF16, FLAGS><<<blocks, kWave * t.rows, 0, s>>>(g, t.kchunk, nti, nfb, omega, order, parts);
 }
 
 template <int VEC, bool BF16, int FLAGS>
