@@ -581,9 +581,35 @@ def test_batch_default_tile():
     grids = [ofl.Grid(a, row_align=4) for a in _small_batch(2)]
     b = ofl.ofl_batch_create([g.handle for g in grids])
     assert ofl.ofl_batch_get_tile(b).as_dict() == dict(
-        vec=0, rows=4, kchunk=4, flags=ofl.OFL_TILE_NT_LOADS | ofl.OFL_TILE_NT_STORES, occupancy=0)
+        vec=0, rows=1, kchunk=4, flags=ofl.OFL_TILE_NT_LOADS | ofl.OFL_TILE_NT_STORES, occupancy=0)
     ofl.ofl_batch_destroy(b)
     for g in grids:
+        g.close()
+
+
+@pytest.mark.parametrize("fusion", [0, ofl.OFL_FUSE_RESIDUAL | ofl.OFL_FUSE_COPYBACK_SWAP])
+@pytest.mark.parametrize("rows,occupancy", [(1, 0), (4, 0), (2, 1)])
+@pytest.mark.parametrize("fmt", [ofl.OFL_COEF_F32, ofl.OFL_COEF_BF16_OFFSET])
+def test_batch_band_order_equals_remap_order(fmt, rows, occupancy, fusion):
+    """The batch hands each XCD runs of consecutive sweep items unless the
+    tile asks for XCD-contiguous ranges: both orders must give bitwise the
+    same p (and, unfused, the same residuals; fused, the same terms summed in
+    other slots), on packed and row-per-wave grids, one work-group per item
+    or a smaller grid walking the list."""
+    say("batch band order fmt", fmt, "rows", rows, "occupancy", occupancy, "fusion", fusion)
+    probs = _small_batch() + [synth.make_problem(40, 66, 30, seed=synth.grid_seed(77))]
+    aligns = [4, 0, 4, 4, 0, 4, 4]
+    base = dict(vec=0, rows=rows, kchunk=3, occupancy=occupancy)
+    flags = ofl.OFL_TILE_NT_LOADS | ofl.OFL_TILE_NT_STORES
+    band, r_band = _batch_run(probs, fmt, ofl.tile(flags=flags, **base), aligns, 5, fusion)
+    remap, r_remap = _batch_run(probs, fmt, ofl.tile(flags=flags | ofl.OFL_TILE_XCD_REMAP, **base), aligns, 5, fusion)
+    for a, g, gr, x, xr in zip(probs, band, remap, r_band, r_remap):
+        assert np.array_equal(g.p, gr.p)
+        assert x == (xr if fusion == 0 else pytest.approx(xr, rel=1e-12))
+    if fmt == ofl.OFL_COEF_F32:
+        for a, g, x in zip(probs[:2], band, r_band):
+            check_against_oracle(a, g, x, 5)
+    for g in band + remap:
         g.close()
 
 
