@@ -251,7 +251,10 @@ typedef struct ofl_tile {
                       0 = one work-group per work item */
 } ofl_tile;
 
-/* Set / read the sweep tile of a grid. EINVAL for values outside the ranges. */
+/* Set / read the sweep tile of a grid. EINVAL for values outside the ranges.
+ * A new grid's tile: vec 4, 2 or 1 for more than 128, 64 or fewer interior
+ * points per row; 4 rows; 4-plane chunks for FP32 coefficients, 2 for the
+ * bfloat16 formats; non-temporal loads. */
 int ofl_set_tile(ofl_grid *g, const ofl_tile *tile);
 int ofl_get_tile(const ofl_grid *g, ofl_tile *tile);
 

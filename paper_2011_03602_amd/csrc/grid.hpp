@@ -95,7 +95,7 @@ namespace ofl {
 // only a search sets deadlines, and it catches this).
 struct Timeout {};
 
-ofl::TileCfg default_tile(int I);
+ofl::TileCfg default_tile(int I, int fmt);
 bool grid_whole_nests(const ofl_grid *g);
 int loop_gene_bits(const ofl_grid *g);
 void decode_loop_gene(const ofl_grid *g, uint32_t gene, unsigned *mask, int level[3]);

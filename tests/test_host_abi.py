@@ -97,6 +97,20 @@ def test_run_validates_arguments():
     g.close()
 
 
+def test_default_tile_follows_row_length_and_format():
+    """A new grid's sweep tile: the vector width from the row length, 4-plane
+    chunks for FP32 coefficients and 2-plane chunks for the bfloat16 formats."""
+    nt = ofl.OFL_TILE_NT_LOADS
+    for (I, fmt), want in {(300, ofl.OFL_COEF_F32): dict(vec=4, rows=4, kchunk=4, flags=nt, occupancy=0),
+                           (100, ofl.OFL_COEF_F32): dict(vec=2, rows=4, kchunk=4, flags=nt, occupancy=0),
+                           (40, ofl.OFL_COEF_F32): dict(vec=1, rows=4, kchunk=4, flags=nt, occupancy=0),
+                           (300, ofl.OFL_COEF_BF16_OFFSET): dict(vec=4, rows=4, kchunk=2, flags=nt, occupancy=0),
+                           (40, ofl.OFL_COEF_BF16): dict(vec=1, rows=4, kchunk=2, flags=nt, occupancy=0)}.items():
+        g = ofl.Grid(synth.make_problem(I, 5, 4), coef_format=fmt)
+        assert ofl.ofl_get_tile(g.handle).as_dict() == want, (I, fmt)
+        g.close()
+
+
 def test_zero_iterations_leave_p_alone():
     a = synth.make_problem(6, 5, 4)
     g = ofl.Grid(a)
