@@ -56,14 +56,15 @@ def kernel_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """Counter-measured HBM bytes per sweep launch, if taken on the current kernel source."""
+def measured_traffic(tile):
+    """Counter-measured HBM bytes per sweep launch, if taken on the current
+    kernel source with the tile the headline ran (else None)."""
     try:
         with open(PROFILE_TRAFFIC) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha256_16") != kernel_hash():
+    if rec.get("kernel_source_sha256_16") != kernel_hash() or rec.get("tile") != tile:
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -652,7 +653,7 @@ def main():
     sweep_us = head["nest_ms_avg"][0] * 1e3
     lup_launch = interior(I, J, K)
     achieved = SWEEP_BYTES["f32"] * lup_launch / (sweep_us * 1e-6) / 1e9
-    traffic = measured_traffic()
+    traffic = measured_traffic(head["tile"])
     roofline = {
         "bound": "hbm",
         "kernel": "sweep_kernel (nest S, FP32 coefficients)",

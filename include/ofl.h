@@ -252,9 +252,11 @@ typedef struct ofl_tile {
 } ofl_tile;
 
 /* Set / read the sweep tile of a grid. EINVAL for values outside the ranges.
- * A new grid's tile: vec 4, 2 or 1 for more than 128, 64 or fewer interior
- * points per row; 4 rows; 4-plane chunks for FP32 coefficients, 2 for the
- * bfloat16 formats; non-temporal loads. */
+ * Until a tile is set here or by ofl_grid_tune, the grid uses its default:
+ * vec 4, 2 or 1 for more than 128, 64 or fewer interior points per row;
+ * 4 rows; 2-plane chunks; non-temporal loads; non-temporal stores for FP32
+ * coefficients, and for the bfloat16 formats while OFL_FUSE_COPYBACK_SWAP is
+ * set (ofl_set_fusion re-derives the default). */
 int ofl_set_tile(ofl_grid *g, const ofl_tile *tile);
 int ofl_get_tile(const ofl_grid *g, ofl_tile *tile);
 

@@ -115,17 +115,22 @@ ofl_tile to_tile(const TileCfg &c) {
     return t;
 }
 
-TileCfg default_tile(int I, int fmt) {
+TileCfg default_tile(int I, int fmt, unsigned fusion) {
     TileCfg t;
     const int interior = I - 2;
     t.vec = interior > 128 ? 4 : (interior > 64 ? 2 : 1);
     t.rows = 4;
-    // bfloat16 coefficients move 32 bytes per point instead of 56, so HBM
-    // needs more waves in flight: 2-plane chunks, twice the work-groups
-    // (measured at 257x257x513: 187.6 against 194.8 us per sweep; FP32 is
-    // best at 4 planes, 319-321 us with 2 to 4).
-    t.kchunk = fmt == OFL_COEF_F32 ? 4 : 2;
+    // 2-plane chunks: twice the work-groups of 4-plane ones keep more loads
+    // in flight. Non-temporal stores of wrk2 for FP32 coefficients, and for
+    // bfloat16 ones when the copy-back is a buffer exchange (the sweep's
+    // output is then next read a whole sweep later). Measured at 257x257x513,
+    // steps of 100 iterations, GLUP/s against 4-plane chunks with NT loads
+    // only: FP32 83.6 / 82.6, fused 103.6 / 99.4; bfloat16-offset 123.1 /
+    // 120.8 (NT stores there: 121.3), fused with NT stores 169.3 against 160.6.
+    t.kchunk = 2;
     t.flags = OFL_TILE_NT_LOADS;
+    if (fmt == OFL_COEF_F32 || (fusion & OFL_FUSE_COPYBACK_SWAP) != 0)
+        t.flags |= OFL_TILE_NT_STORES;
     t.occupancy = 0;
     return t;
 }
@@ -939,7 +944,7 @@ int ofl_grid_create(const ofl_grid_desc *d, ofl_grid **out) {
         g->arena_bytes = d->dev_arena_bytes;
         g->want_device = d->device;
         g->row_align = d->row_align;
-        g->tile = default_tile(d->I, d->coef_format);
+        g->tile = default_tile(d->I, d->coef_format, 0);
         if (g->fmt != OFL_COEF_F32)
             encode_bf16(g.get());
         *out = g.release();
@@ -1113,6 +1118,8 @@ int ofl_set_fusion(ofl_grid *g, unsigned flags) {
         if (flags != 0 && g->batch_refs > 0)
             fail(OFL_ESTATE, "a grid inside a batch cannot swap its buffers; destroy the batch first");
         g->fusion = flags;
+        if (!g->tile_chosen)
+            g->tile = default_tile(g->I, g->fmt, flags);
     });
 }
 
@@ -1124,6 +1131,7 @@ int ofl_set_tile(ofl_grid *g, const ofl_tile *tile) {
         if (!tile_valid(*tile, &why))
             fail(OFL_EINVAL, why);
         g->tile = to_cfg(*tile);
+        g->tile_chosen = true;
     });
 }
 

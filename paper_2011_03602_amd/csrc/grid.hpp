@@ -28,6 +28,7 @@ struct ofl_grid {
     int mode = OFL_XFER_HOISTED;
     int level[3] = {OFL_LEVEL_K, OFL_LEVEL_K, OFL_LEVEL_K};  // where each GPU nest's region opens
     ofl::TileCfg tile;
+    bool tile_chosen = false;  // set by ofl_set_tile or the tuner; else the default follows the fusion
     bool in_region = false;
     ofl::Validity valid = ofl::fresh_validity();
 
@@ -95,7 +96,7 @@ namespace ofl {
 // only a search sets deadlines, and it catches this).
 struct Timeout {};
 
-ofl::TileCfg default_tile(int I, int fmt);
+ofl::TileCfg default_tile(int I, int fmt, unsigned fusion);
 bool grid_whole_nests(const ofl_grid *g);
 int loop_gene_bits(const ofl_grid *g);
 void decode_loop_gene(const ofl_grid *g, uint32_t gene, unsigned *mask, int level[3]);

@@ -707,6 +707,7 @@ int ofl_grid_tune(ofl_grid *g, const ofl_ga_params *ga_in, ofl_tune_result *out)
         g->mask = mask;
         g->mode = mode;
         g->tile = to_cfg(res.best);
+        g->tile_chosen = true;
         *out = res;
     });
 }

@@ -31,5 +31,6 @@ def test_help_lists_every_configuration():
 def test_traffic_record_names_its_kernel_source():
     rec = json.load(open(os.path.join(ROOT, "profiles", "sweep_f32_257x257x513_traffic.json")))
     assert len(rec["kernel_source_sha256_16"]) == 16
+    assert set(rec["tile"]) == {"vec", "rows", "kchunk", "flags", "occupancy"}
     assert rec["hbm_bytes_per_launch"] == rec["hbm_read_bytes_per_launch"] + rec["hbm_write_bytes_per_launch"]
     assert rec["algorithmic_bytes_per_launch"] == 56 * 255 * 255 * 511
