@@ -581,7 +581,13 @@ def test_batch_default_tile():
     grids = [ofl.Grid(a, row_align=4) for a in _small_batch(2)]
     b = ofl.ofl_batch_create([g.handle for g in grids])
     assert ofl.ofl_batch_get_tile(b).as_dict() == dict(
-        vec=0, rows=1, kchunk=4, flags=ofl.OFL_TILE_NT_LOADS | ofl.OFL_TILE_NT_STORES, occupancy=0)
+        vec=0, rows=1, kchunk=2, flags=ofl.OFL_TILE_NT_LOADS | ofl.OFL_TILE_NT_STORES, occupancy=0)
+    ofl.ofl_batch_destroy(b)
+    for g in grids:
+        g.close()
+    grids = [ofl.Grid(a, row_align=4, coef_format=ofl.OFL_COEF_BF16_OFFSET) for a in _small_batch(2)]
+    b = ofl.ofl_batch_create([g.handle for g in grids])
+    assert ofl.ofl_batch_get_tile(b).kchunk == 4
     ofl.ofl_batch_destroy(b)
     for g in grids:
         g.close()
