@@ -11,7 +11,8 @@
 // Gene layout (bit 0 first):
 //   bits 0-1  vec       00:1 01:2 10:4 11: not buildable
 //   bits 2-3  rows      1, 2, 4, 8
-//   bits 4-6  kchunk    4, 8, ..., 512
+//   bits 4-6  kchunk    1, 2, 4, ..., 128 (the short chunks measure best on
+//                       MI355X: more work-groups keep more loads in flight)
 //   bits 7-11 flags     OFL_TILE_NT_LOADS | OFL_TILE_NT_STORES | OFL_TILE_PREFETCH |
 //                       OFL_TILE_MARCH_J | OFL_TILE_XCD_REMAP
 //   bits 12-13 (batch)  occupancy 0 (one work-group per item), 2, 4, 8 per CU
@@ -54,7 +55,7 @@ bool decode(uint32_t gene, bool batch, TileCfg *t) {
         return false;
     t->vec = v == 0 ? 1 : (v == 1 ? 2 : 4);
     t->rows = 1 << ((gene >> 2) & 3u);
-    t->kchunk = 4 << ((gene >> 4) & 7u);
+    t->kchunk = 1 << ((gene >> 4) & 7u);
     t->flags = static_cast<int>((gene >> 7) & 31u);
     const int occ = static_cast<int>((gene >> 12) & 3u);
     t->occupancy = batch ? (occ == 0 ? 0 : (1 << occ)) : 0;
@@ -72,7 +73,7 @@ uint32_t encode(const TileCfg &t, bool batch) {
         ++r;
     g |= static_cast<uint32_t>(r) << 2;
     int k = 0;
-    while ((4 << k) < t.kchunk && k < 7)
+    while ((1 << k) < t.kchunk && k < 7)
         ++k;
     g |= static_cast<uint32_t>(k) << 4;
     g |= static_cast<uint32_t>(t.flags & 31) << 7;
