@@ -97,7 +97,8 @@ typedef struct ofl_grid_desc {
     const float *coef[12];  /* host, I*J*K each, read-only; order a0..a3 b0..b2 c0..c2 bnd wrk1 */
     void *stream;           /* hipStream_t to launch on, borrowed; NULL: the library makes one */
     void *dev_arena;        /* optional caller-owned device memory (e.g. from PyTorch), 256-byte
-                               aligned, at least ofl_grid_device_bytes() bytes; NULL: hipMalloc */
+                               aligned, at least ofl_grid_device_bytes(I, J, K, coef_format,
+                               row_align) bytes; NULL: hipMalloc */
     size_t dev_arena_bytes; /* size of dev_arena */
     int device;             /* HIP device ordinal; -1: the device current at creation */
     int row_align;          /* elements every device row is padded to: 0 for a 128-byte line (32 FP32 or
@@ -106,10 +107,12 @@ typedef struct ofl_grid_desc {
                                (ofl_batch_create). Results do not depend on it. */
 } ofl_grid_desc;
 
-/* Device bytes a grid of this shape and format needs (arena sizing), with the
- * default row alignment; a smaller desc.row_align needs no more.
- * Returns OFL_EINVAL for a dimension below 3 or an unknown format. */
-int ofl_grid_device_bytes(int I, int J, int K, int coef_format, size_t *bytes);
+/* Device bytes a grid of this shape, format and row alignment (as in
+ * desc.row_align: 0, 4, 8, 16 or 32) needs: the size a dev_arena must have.
+ * A compact row alignment can need more than the default one, because it also
+ * pads every plane to 64 elements. Returns OFL_EINVAL for a dimension below 3,
+ * an unknown format or row alignment, or a NULL bytes. */
+int ofl_grid_device_bytes(int I, int J, int K, int coef_format, int row_align, size_t *bytes);
 
 /* Create a grid handle over the caller's host arrays (the CPU program's
  * variables, Sec. 4.2.2). The host arrays are borrowed and must outlive the
@@ -191,7 +194,10 @@ int ofl_get_regions(const ofl_grid *g, unsigned *mask, int level[3], int *xfer_m
 int ofl_jacobi_run(ofl_grid *g, int iters, float omega, double *gosa_out);
 
 /* Residual of the current iterate without changing it: S with omega = 1 into
- * wrk2, then R; no copy-back. Uses the devices of the current mask. */
+ * wrk2, then R; no copy-back. Uses the devices of the current mask. The paper
+ * defines no such call: it is the offloaded program's own residual nest, run
+ * once on the current iterate, for a caller that wants a convergence check
+ * outside the iteration loop. */
 int ofl_residual(ofl_grid *g, double *gosa_out);
 
 /* Data region (the hoisting of Sec. 3.2.1 across calls, like an OpenACC data
@@ -214,8 +220,10 @@ int ofl_data_exit(ofl_grid *g);
  * the interior and wrk2's device copy first receives p's boundary). Results
  * equal the unfused path's up to the residual's summation order; wrk2's device
  * content after a run is unspecified (it is scratch). Other genes, per-iteration
- * placement and batched runs ignore the setting. EINVAL for unknown bits;
- * ESTATE while the grid belongs to a batch. */
+ * placement and batched runs ignore the setting. The fused residual sums in
+ * FP64 only, so OFL_FUSE_RESIDUAL on a grid created with OFL_SUM_KAHAN_F32 is
+ * refused (ENOTSUP) rather than reporting an FP64 sum as a compensated one.
+ * EINVAL for unknown bits; ESTATE while the grid belongs to a batch. */
 #define OFL_FUSE_RESIDUAL 1u
 #define OFL_FUSE_COPYBACK_SWAP 2u
 int ofl_set_fusion(ofl_grid *g, unsigned flags);
@@ -329,7 +337,13 @@ int ofl_plan_nests(const ofl_nest_vars *nests, int nnests, int narrays, uint32_t
  * arrays, and the arrays referenced after the loop (p). EINVAL on NULL. */
 int ofl_program_vars(ofl_nest_vars out[3], uint32_t *live_after);
 
-/* ---- many independent grids in one launch sequence ------------------------- */
+/* ---- many independent grids in one launch sequence -------------------------
+ * Not a step of the paper's method: the paper offloads one program run at a
+ * time. A batch serves many independent instances of the offloaded program
+ * (grids of uneven sizes) with the same gene (111, hoisted) in one graph
+ * launch. Errors: a device error in a batched call makes the batch and every
+ * grid in it unusable (OFL_EDEVICE from then on; destroy the batch, then the
+ * grids); a device error in ofl_batch_create leaves the grids as they were. */
 typedef struct ofl_batch ofl_batch;
 
 /* Group n grids (all on one device, one coefficient format and sum mode) for
@@ -354,7 +368,9 @@ int ofl_batch_get_tile(const ofl_batch *b, ofl_tile *tile);
  * batched sweep also emits each grid's residual partials, and/or the copy-back
  * becomes an exchange of every grid's p and wrk2 buffers (odd iterations read
  * a second view table with the two exchanged; after a run of odd length the
- * grids keep the exchange). EINVAL for unknown bits. */
+ * grids keep the exchange). EINVAL for unknown bits; ENOTSUP for
+ * OFL_FUSE_RESIDUAL on a batch of OFL_SUM_KAHAN_F32 grids (the fused residual
+ * sums in FP64 only). */
 int ofl_batch_set_fusion(ofl_batch *b, unsigned flags);
 
 /* iters x (S, R, C) on the GPU for every grid of the batch, inside the

@@ -130,7 +130,7 @@ class OflError(RuntimeError):
 _lib_handle = None
 
 _SIGS = {
-    "ofl_grid_device_bytes": ([ctypes.c_int] * 4 + [ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "ofl_grid_device_bytes": ([ctypes.c_int] * 5 + [ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "ofl_grid_create": ([ctypes.POINTER(OflGridDesc), ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "ofl_grid_destroy": ([ctypes.c_void_p], None),
     "ofl_set_offload_mask": ([ctypes.c_void_p, ctypes.c_uint, ctypes.c_int], ctypes.c_int),
@@ -211,9 +211,9 @@ def _check(rc: int):
         raise OflError(rc, ofl_last_error())
 
 
-def ofl_grid_device_bytes(I: int, J: int, K: int, coef_format: int = OFL_COEF_F32) -> int:
+def ofl_grid_device_bytes(I: int, J: int, K: int, coef_format: int = OFL_COEF_F32, row_align: int = 0) -> int:
     out = ctypes.c_size_t()
-    _check(lib().ofl_grid_device_bytes(I, J, K, coef_format, ctypes.byref(out)))
+    _check(lib().ofl_grid_device_bytes(I, J, K, coef_format, row_align, ctypes.byref(out)))
     return out.value
 
 
@@ -495,7 +495,7 @@ class Grid:
         if torch_memory:
             import torch
 
-            nbytes = ofl_grid_device_bytes(I, J, K, coef_format)
+            nbytes = ofl_grid_device_bytes(I, J, K, coef_format, row_align)
             arena = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
             self.stream = torch.cuda.Stream()
             self._torch_keep += [arena, self.stream]

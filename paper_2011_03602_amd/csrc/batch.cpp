@@ -483,7 +483,12 @@ int ofl_batch_create(ofl_grid *const *grids, int n, const ofl_tile *tile, ofl_ba
                 fail(OFL_EINVAL, "all grids of a batch must live on one device");
         hip_check(hipSetDevice(b->device), "hipSetDevice");
         hip_check(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking), "hipStreamCreate(batch)");
-        b->cu_count = device_cu_count(b->device);
+        try {
+            b->cu_count = device_cu_count(b->device);
+        } catch (...) {
+            (void)hipStreamDestroy(b->stream);
+            throw;
+        }
         for (ofl_grid *g : b->grids)
             g->batch_refs += 1;
         made = b.release();
@@ -496,7 +501,7 @@ int ofl_batch_create(ofl_grid *const *grids, int n, const ofl_tile *tile, ofl_ba
 void ofl_batch_destroy(ofl_batch *b) { batch_destroy_impl(b); }
 
 int ofl_batch_set_tile(ofl_batch *b, const ofl_tile *tile) {
-    return guarded(nullptr, [&] {
+    return batch_call(b, [&] {
         if (!b || !tile)
             fail(OFL_EINVAL, "NULL argument");
         std::string why;
@@ -514,11 +519,13 @@ int ofl_batch_set_tile(ofl_batch *b, const ofl_tile *tile) {
 }
 
 int ofl_batch_set_fusion(ofl_batch *b, unsigned flags) {
-    return guarded(nullptr, [&] {
+    return batch_call(b, [&] {
         if (!b)
             fail(OFL_EINVAL, "NULL batch handle");
         if (flags & ~static_cast<unsigned>(OFL_FUSE_RESIDUAL | OFL_FUSE_COPYBACK_SWAP))
             fail(OFL_EINVAL, "unknown fusion bits");
+        if ((flags & OFL_FUSE_RESIDUAL) && b->sum_mode != OFL_SUM_F64)
+            fail(OFL_ENOTSUP, "the fused residual sums in FP64 only; this batch asks for compensated FP32");
         if (flags != b->fusion) {
             hip_check(hipSetDevice(b->device), "hipSetDevice");
             hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
@@ -537,7 +544,7 @@ int ofl_batch_get_tile(const ofl_batch *b, ofl_tile *tile) {
 }
 
 int ofl_batch_run(ofl_batch *b, int iters, float omega, double *gosa_out) {
-    return guarded(nullptr, [&] {
+    return batch_call(b, [&] {
         if (!b)
             fail(OFL_EINVAL, "NULL batch handle");
         if (iters < 0)

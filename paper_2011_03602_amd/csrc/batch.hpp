@@ -36,6 +36,8 @@ struct ofl_batch {
     int graph_iters = -1;
     float graph_omega = NAN;
     unsigned graph_fusion = 0;
+
+    bool broken = false;  // a device error left the batch (and its grids) unusable
 };
 
 namespace ofl {
@@ -52,5 +54,28 @@ int batch_auto_vec(int I);
 bool batch_packed(int I, int J, int pitch, const ofl::TileCfg &t, int *vec, int *nseg);
 int batch_auto_vec(int I);
 bool batch_auto_vec_tile(const ofl_tile &t);
+
+// Run f() for a batch handle: refused once a device error made the batch
+// unusable; a device error in f marks the batch and every grid in it so, since
+// their device state is then unknown (OFL_EDEVICE is sticky).
+template <class F>
+int batch_call(ofl_batch *b, F &&f) {
+    if (!b) {
+        set_last_error("NULL batch handle");
+        return OFL_EINVAL;
+    }
+    if (b->broken) {
+        set_last_error("batch handle unusable after an earlier device error");
+        return OFL_EDEVICE;
+    }
+    bool dev_err = false;
+    const int rc = guarded(&dev_err, f);
+    if (dev_err) {
+        b->broken = true;
+        for (ofl_grid *g : b->grids)
+            g->broken = true;
+    }
+    return rc;
+}
 
 }  // namespace ofl

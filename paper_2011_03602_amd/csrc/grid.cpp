@@ -26,6 +26,8 @@ thread_local std::string t_last_error;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+bool row_align_valid(int a) { return a == 0 || a == 4 || a == 8 || a == 16 || a == 32; }
+
 }  // namespace
 
 void set_last_error(const std::string &msg) { t_last_error = msg; }
@@ -164,31 +166,45 @@ void grid_ensure_device(ofl_grid *g) {
     if (dev >= count)
         fail(OFL_EINVAL, "desc.device is not a valid HIP device ordinal");
     hip_check(hipSetDevice(dev), "hipSetDevice");
+    const Layout lay = make_layout(g->I, g->J, g->K, g->fmt, g->row_align);
+    if (g->arena && g->arena_bytes < lay.total)
+        fail(OFL_ENOMEM, "dev_arena is smaller than ofl_grid_device_bytes()");
+    // Take the block and the stream, and zero the block, before the grid
+    // records any of it: a failure on the way releases what was taken and
+    // leaves the grid without device state, as before the call.
+    char *block = static_cast<char *>(g->arena);
+    bool own_block = false;
+    hipStream_t stream = static_cast<hipStream_t>(g->user_stream);
+    bool own_stream = false;
+    try {
+        if (!block) {
+            void *ptr = nullptr;
+            const hipError_t e = hipMalloc(&ptr, lay.total);
+            if (e != hipSuccess)
+                fail(OFL_ENOMEM, std::string("hipMalloc of the grid's device block failed: ") + hipGetErrorString(e));
+            block = static_cast<char *>(ptr);
+            own_block = true;
+        }
+        if (!stream) {
+            hip_check(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking), "hipStreamCreate");
+            own_stream = true;
+        }
+        // Zero the whole block once (guards and padding included) so that every
+        // value a wave may read past a row end is defined.
+        launch_fill_zero(block, lay.total, stream);
+    } catch (...) {
+        if (own_stream)
+            (void)hipStreamDestroy(stream);
+        if (own_block)
+            (void)hipFree(block);
+        throw;
+    }
     g->device = dev;
-    g->lay = make_layout(g->I, g->J, g->K, g->fmt, g->row_align);
-    if (g->arena) {
-        if (g->arena_bytes < g->lay.total)
-            fail(OFL_ENOMEM, "dev_arena is smaller than ofl_grid_device_bytes()");
-        g->block = static_cast<char *>(g->arena);
-        g->own_block = false;
-    } else {
-        void *ptr = nullptr;
-        const hipError_t e = hipMalloc(&ptr, g->lay.total);
-        if (e != hipSuccess)
-            fail(OFL_ENOMEM, std::string("hipMalloc of the grid's device block failed: ") + hipGetErrorString(e));
-        g->block = static_cast<char *>(ptr);
-        g->own_block = true;
-    }
-    if (g->user_stream) {
-        g->stream = static_cast<hipStream_t>(g->user_stream);
-        g->own_stream = false;
-    } else {
-        hip_check(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking), "hipStreamCreate");
-        g->own_stream = true;
-    }
-    // Zero the whole block once (guards and padding included) so that every
-    // value a wave may read past a row end is defined.
-    launch_fill_zero(g->block, g->lay.total, g->stream);
+    g->lay = lay;
+    g->block = block;
+    g->own_block = own_block;
+    g->stream = stream;
+    g->own_stream = own_stream;
     GridView &v = g->view;
     v.p = reinterpret_cast<float *>(g->block + g->lay.off[OFL_ARR_P]);
     v.wrk2 = reinterpret_cast<float *>(g->block + g->lay.off[OFL_ARR_WRK2]);
@@ -676,6 +692,7 @@ void grid_run_loop(ofl_grid *g, int iters, float omega, int nests) {
             if (gpu)
                 grid_ensure_device(g);
             xs.clear();
+            const Validity before = g->valid;
             plan_before(it, nest, gpu, g->mode, g->valid, xs);
             if (gpu && g->level[nest] != OFL_LEVEL_K) {
                 // The planner's whole-array decisions stand; hoisted ones run
@@ -695,6 +712,16 @@ void grid_run_loop(ofl_grid *g, int iters, float omega, int nests) {
                 if (!per_iter)
                     out = -1;
                 gpu_nest_regions(g, nest, omega, per_iter, ins, out);
+                // Per iteration, the regions moved only the rows they read (a
+                // residual or copy-back region skips the boundary layer), so an
+                // array that was not on the device before holds just those rows
+                // there: the device copy is not whole and must not count as
+                // valid. The host copy is whole (the rows came from it, and
+                // written rows went back), so a later whole-array use re-sends it.
+                if (per_iter)
+                    for (int a : ins)
+                        if (!before.dev[a])
+                            g->valid.dev[a] = 0;
                 continue;
             }
             grid_exec(g, xs);
@@ -752,23 +779,6 @@ void encode_bf16(ofl_grid *g) {
         g->enc[a].resize(n);
         cpu_encode_bf16(x, n, b, g->enc[a].data());
     }
-}
-
-template <class F>
-int grid_call(ofl_grid *g, F &&f) {
-    if (!g) {
-        set_last_error("NULL grid handle");
-        return OFL_EINVAL;
-    }
-    if (g->broken) {
-        set_last_error("grid handle unusable after an earlier device error");
-        return OFL_EDEVICE;
-    }
-    bool dev_err = false;
-    const int rc = guarded(&dev_err, f);
-    if (dev_err && g->dev_ready)
-        g->broken = true;
-    return rc;
 }
 
 }  // namespace
@@ -891,7 +901,7 @@ const char *ofl_last_error(void) { return t_last_error.c_str(); }
 
 const char *ofl_version(void) { return "ofl 0.1.0 (gfx950)"; }
 
-int ofl_grid_device_bytes(int I, int J, int K, int coef_format, size_t *bytes) {
+int ofl_grid_device_bytes(int I, int J, int K, int coef_format, int row_align, size_t *bytes) {
     return guarded(nullptr, [&] {
         if (!bytes)
             fail(OFL_EINVAL, "bytes is NULL");
@@ -899,7 +909,9 @@ int ofl_grid_device_bytes(int I, int J, int K, int coef_format, size_t *bytes) {
             fail(OFL_EINVAL, "every grid dimension must be >= 3");
         if (coef_format < OFL_COEF_F32 || coef_format > OFL_COEF_BF16_OFFSET)
             fail(OFL_EINVAL, "unknown coef_format");
-        *bytes = make_layout(I, J, K, coef_format).total;
+        if (!row_align_valid(row_align))
+            fail(OFL_EINVAL, "row_align must be 0, 4, 8, 16 or 32");
+        *bytes = make_layout(I, J, K, coef_format, row_align).total;
     });
 }
 
@@ -923,8 +935,7 @@ int ofl_grid_create(const ofl_grid_desc *d, ofl_grid **out) {
         for (int a = 0; a < kNCoef; ++a)
             if (!d->coef[a])
                 fail(OFL_EINVAL, "every coefficient array must be given");
-        if (d->row_align != 0 && d->row_align != 4 && d->row_align != 8 && d->row_align != 16 &&
-            d->row_align != 32)
+        if (!row_align_valid(d->row_align))
             fail(OFL_EINVAL, "row_align must be 0, 4, 8, 16 or 32");
         if (d->dev_arena && (reinterpret_cast<uintptr_t>(d->dev_arena) % 256) != 0)
             fail(OFL_EINVAL, "dev_arena must be 256-byte aligned");
@@ -1117,6 +1128,8 @@ int ofl_set_fusion(ofl_grid *g, unsigned flags) {
             fail(OFL_EINVAL, "unknown fusion bits");
         if (flags != 0 && g->batch_refs > 0)
             fail(OFL_ESTATE, "a grid inside a batch cannot swap its buffers; destroy the batch first");
+        if ((flags & OFL_FUSE_RESIDUAL) && g->sum_mode != OFL_SUM_F64)
+            fail(OFL_ENOTSUP, "the fused residual sums in FP64 only; this grid asks for compensated FP32");
         g->fusion = flags;
         if (!g->tile_chosen)
             g->tile = default_tile(g->I, g->fmt, flags);

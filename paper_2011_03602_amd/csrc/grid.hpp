@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "abi_util.hpp"
 #include "ofl_internal.hpp"
 #include "planner.hpp"
 
@@ -108,5 +109,26 @@ void grid_run_loop(ofl_grid *g, int iters, float omega, int nests);
 double grid_fetch_gosa(ofl_grid *g);
 void grid_swap_p_wrk2(ofl_grid *g);
 void grid_sync_wrk2_boundary(ofl_grid *g);
+
+// Run f() for a grid handle: a handle that an earlier device error made
+// unusable is refused (OFL_EDEVICE is sticky), and a device error raised once
+// the grid's device state exists makes it so. Before that (no GPU, a failed
+// first allocation) the handle stays usable, e.g. for an all-CPU gene.
+template <class F>
+int grid_call(ofl_grid *g, F &&f) {
+    if (!g) {
+        set_last_error("NULL grid handle");
+        return OFL_EINVAL;
+    }
+    if (g->broken) {
+        set_last_error("grid handle unusable after an earlier device error");
+        return OFL_EDEVICE;
+    }
+    bool dev_err = false;
+    const int rc = guarded(&dev_err, f);
+    if (dev_err && g->dev_ready)
+        g->broken = true;
+    return rc;
+}
 
 }  // namespace ofl

@@ -516,7 +516,7 @@ int ofl_ga_search(int bits, const ofl_ga_params *ga_in, uint32_t seed_gene, ofl_
 
 int ofl_grid_search_offload(ofl_grid *g, const ofl_ga_params *ga_in, int iters, float omega,
                             ofl_offload_result *out) {
-    return guarded(nullptr, [&] {
+    return grid_call(g, [&] {
         if (!g || !out)
             fail(OFL_EINVAL, "NULL argument");
         if (g->broken)
@@ -563,7 +563,7 @@ int ofl_grid_search_offload(ofl_grid *g, const ofl_ga_params *ga_in, int iters, 
 
 int ofl_grid_search_loops(ofl_grid *g, const ofl_ga_params *ga_in, int iters, float omega, int xfer_mode,
                           double time_limit_ms, ofl_loop_search_result *out) {
-    return guarded(nullptr, [&] {
+    return grid_call(g, [&] {
         if (!g || !out)
             fail(OFL_EINVAL, "NULL argument");
         if (g->broken)
@@ -657,7 +657,7 @@ int ofl_grid_search_loops(ofl_grid *g, const ofl_ga_params *ga_in, int iters, fl
 }
 
 int ofl_grid_tune(ofl_grid *g, const ofl_ga_params *ga_in, ofl_tune_result *out) {
-    return guarded(nullptr, [&] {
+    return grid_call(g, [&] {
         if (!g || !out)
             fail(OFL_EINVAL, "NULL argument");
         if (g->broken)
@@ -714,7 +714,7 @@ int ofl_grid_tune(ofl_grid *g, const ofl_ga_params *ga_in, ofl_tune_result *out)
 }
 
 int ofl_batch_tune(ofl_batch *b, const ofl_ga_params *ga_in, ofl_tune_result *out) {
-    return guarded(nullptr, [&] {
+    return batch_call(b, [&] {
         if (!b || !out)
             fail(OFL_EINVAL, "NULL argument");
         const ofl_ga_params ga = defaults_or(ga_in);

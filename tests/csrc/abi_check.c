@@ -132,7 +132,9 @@ static int run_formats(int I, int J, int K) {
         CHECK(ofl_set_tile(g, &t) == OFL_OK);
         t.vec = 3;
         CHECK(ofl_set_tile(g, &t) == OFL_EINVAL);
-        CHECK(ofl_set_fusion(g, OFL_FUSE_RESIDUAL | OFL_FUSE_COPYBACK_SWAP) == OFL_OK);
+        /* the fused residual sums in FP64 only: refused where the grid asks for compensated FP32 */
+        CHECK(ofl_set_fusion(g, OFL_FUSE_RESIDUAL | OFL_FUSE_COPYBACK_SWAP) == (fmt == 2 ? OFL_ENOTSUP : OFL_OK));
+        CHECK(ofl_set_fusion(g, OFL_FUSE_COPYBACK_SWAP) == OFL_OK);
         CHECK(ofl_set_fusion(g, 8u) == OFL_EINVAL);
         CHECK(ofl_jacobi_run(g, -1, 0.8f, &gosa) == OFL_EINVAL);
         CHECK(ofl_jacobi_run(g, 1, 0.0f, &gosa) == OFL_EINVAL);
@@ -206,8 +208,8 @@ int main(void) {
         drop(&pc);
     }
     size_t bytes = 0;
-    CHECK(ofl_grid_device_bytes(257, 257, 513, OFL_COEF_F32, &bytes) == OFL_OK && bytes > 14ull * 257 * 257 * 513 * 4);
-    CHECK(ofl_grid_device_bytes(2, 3, 3, OFL_COEF_F32, &bytes) == OFL_EINVAL);
+    CHECK(ofl_grid_device_bytes(257, 257, 513, OFL_COEF_F32, 0, &bytes) == OFL_OK && bytes > 14ull * 257 * 257 * 513 * 4);
+    CHECK(ofl_grid_device_bytes(2, 3, 3, OFL_COEF_F32, 0, &bytes) == OFL_EINVAL);
 
     /* the planner, every gene and placement, with a too-small output */
     for (unsigned mask = 0; mask < 8; ++mask)

@@ -328,6 +328,20 @@ def test_torch_memory_and_stream():
     g.close()
 
 
+@pytest.mark.parametrize("dims,row_align", [((96, 33, 65), 4), ((32, 33, 65), 32), ((45, 29, 23), 8)])
+def test_torch_arena_sized_for_compact_rows(dims, row_align):
+    """An arena of exactly ofl_grid_device_bytes(..., row_align) bytes holds a
+    grid with compact rows (whose planes are padded to 64 elements, so it can
+    need more than 128-byte rows)."""
+    say("torch arena, compact rows", dims, row_align)
+    a = synth.make_problem(*dims, seed=9)
+    g = ofl.Grid(a, torch_memory=True, row_align=row_align)
+    assert g.desc.dev_arena_bytes == ofl.ofl_grid_device_bytes(*dims, ofl.OFL_COEF_F32, row_align)
+    gosa = ofl.ofl_jacobi_run(g.handle, 6, OMEGA)
+    check_against_oracle(a, g, gosa, 6)
+    g.close()
+
+
 # ------------------------------------------------ determinism and semantics
 
 
@@ -441,6 +455,21 @@ def test_fused_runs_hand_over_state_to_unfused_runs_and_cpu_nests():
     r = ofl.ofl_jacobi_run(g.handle, 3, OMEGA)    # p re-uploaded: the boundary copy is redone
     check_against_oracle(a, g, r, 10)
     g.close()
+
+
+def test_fused_residual_refused_for_a_compensated_batch():
+    say("fused residual + compensated batch")
+    grids = [ofl.Grid(a, sum_mode=ofl.OFL_SUM_KAHAN_F32) for a in _small_batch(2)]
+    b = ofl.ofl_batch_create([g.handle for g in grids])
+    with pytest.raises(ofl.OflError) as e:
+        ofl.ofl_batch_set_fusion(b, ofl.OFL_FUSE_RESIDUAL)
+    assert e.value.code == ofl.OFL_ENOTSUP
+    ofl.ofl_batch_set_fusion(b, ofl.OFL_FUSE_COPYBACK_SWAP)
+    gosa = ofl.ofl_batch_run(b, 3, OMEGA, len(grids))
+    ofl.ofl_batch_destroy(b)
+    for a, g, x in zip(_small_batch(2), grids, gosa):
+        check_against_oracle(a, g, x, 3)
+        g.close()
 
 
 def test_fusion_rejected_inside_a_batch():

@@ -72,6 +72,32 @@ def test_every_region_level_matches_whole_nests(case, levels, mode):
     g.close()
 
 
+@pytest.mark.parametrize("then", ["run", "data_region"])
+@pytest.mark.parametrize("mask,levels", [(6, [0, 2, 2]), (2, [0, 1, 0]), (4, [0, 0, 2]), (7, [1, 2, 1]),
+                                         (7, [2, 1, 2]), (3, [2, 2, 0])])
+def test_split_per_iteration_regions_then_whole_nests(mask, levels, then):
+    """Per iteration, residual and copy-back regions below the k loop move
+    only the rows they read, not p's boundary layer. Those device copies must
+    not count as whole: gene 111 with hoisted transfers on the same handle
+    afterwards (a plain run, or one inside a data region) has to send p again.
+    Checked against the oracle over both runs, boundary bitwise unchanged."""
+    say("split per-iteration gene", mask, levels, "then gene 111 hoisted,", then)
+    a = synth.make_problem(*SHAPE, seed=41)
+    p_ref, g_ref = oracle.jacobi(a, 2 * ITERS, float(OMEGA))
+    g = ofl.Grid(a)
+    ofl.ofl_set_regions(g.handle, mask, levels, ofl.OFL_XFER_PER_ITER)
+    ofl.ofl_jacobi_run(g.handle, ITERS, OMEGA)
+    ofl.ofl_set_offload_mask(g.handle, ofl.OFL_MASK_ALL_GPU, ofl.OFL_XFER_HOISTED)
+    if then == "data_region":
+        ofl.ofl_data_enter(g.handle)
+    gosa = ofl.ofl_jacobi_run(g.handle, ITERS, OMEGA)
+    if then == "data_region":
+        ofl.ofl_data_exit(g.handle)
+    assert boundary_equal(g.p, a["p"])
+    assert p_rel_err(g.p, p_ref) <= TOL_P_F32 and rel_err(gosa, g_ref) <= TOL_GOSA_F32
+    g.close()
+
+
 @pytest.mark.parametrize("mode", [ofl.OFL_XFER_HOISTED, ofl.OFL_XFER_PER_ITER])
 @pytest.mark.parametrize("mask,levels", [(1, [2, 0, 0]), (3, [1, 2, 0]), (6, [0, 1, 2]), (5, [1, 0, 2]),
                                          (4, [0, 0, 1]), (2, [0, 2, 0])])

@@ -79,6 +79,41 @@ def test_create_validates_arguments():
         ofl.ofl_grid_destroy(ofl.ofl_grid_create(_desc(a, row_align=good)))
 
 
+def test_device_bytes_follow_the_row_alignment():
+    """A compact row alignment also pads each plane to 64 elements, so it can
+    need more device memory than 128-byte rows: the arena size must follow
+    desc.row_align. Pinned on two shapes where it does (FP32, 12 arrays of
+    coefficients + p + wrk2 with their guards, staging, partials)."""
+    assert ofl.ofl_grid_device_bytes(96, 33, 65, ofl.OFL_COEF_F32, 4) == 12_603_392
+    assert ofl.ofl_grid_device_bytes(96, 33, 65, ofl.OFL_COEF_F32, 0) == 12_488_704
+    assert ofl.ofl_grid_device_bytes(32, 33, 65, ofl.OFL_COEF_F32, 32) == 4_366_336
+    assert ofl.ofl_grid_device_bytes(32, 33, 65, ofl.OFL_COEF_F32, 0) == 4_251_648
+    # a lower bound from the layout's rules, for every alignment and format
+    for I, J, K in [(3, 3, 3), (33, 33, 65), (97, 41, 12), (161, 7, 9)]:
+        for fmt, eb in ((ofl.OFL_COEF_F32, 4), (ofl.OFL_COEF_BF16_OFFSET, 2)):
+            for ra in (0, 4, 8, 16, 32):
+                align = ra or (32 if fmt == ofl.OFL_COEF_F32 else 64)
+                pitch = -(-I // align) * align
+                plane = pitch * J if ra == 0 else -(-(pitch * J) // 64) * 64
+                need = 12 * (plane * K + 2 * 1024) * eb + 2 * (plane * K + 2 * 1024) * 4 + I * J * K * 4
+                assert ofl.ofl_grid_device_bytes(I, J, K, fmt, ra) >= need, (I, J, K, fmt, ra)
+    for bad in (1, 3, 64, -4):
+        with pytest.raises(ofl.OflError) as e:
+            ofl.ofl_grid_device_bytes(33, 33, 65, ofl.OFL_COEF_F32, bad)
+        assert e.value.code == ofl.OFL_EINVAL and "row_align" in ofl.ofl_last_error()
+
+
+def test_fused_residual_refused_for_compensated_sums():
+    """The fused residual sums in FP64 only: a grid that asks for the
+    compensated FP32 sum cannot have it fused (a copy-back exchange alone is fine)."""
+    g = ofl.Grid(synth.make_problem(6, 5, 4), sum_mode=ofl.OFL_SUM_KAHAN_F32)
+    with pytest.raises(ofl.OflError) as e:
+        ofl.ofl_set_fusion(g.handle, ofl.OFL_FUSE_RESIDUAL)
+    assert e.value.code == ofl.OFL_ENOTSUP and "FP64" in ofl.ofl_last_error()
+    ofl.ofl_set_fusion(g.handle, ofl.OFL_FUSE_COPYBACK_SWAP)
+    g.close()
+
+
 def test_run_validates_arguments():
     g = ofl.Grid(synth.make_problem(6, 5, 4))
     h = g.handle
