@@ -282,10 +282,13 @@ def test_bf16_offset_storage(mid):
     g, gosa = run_gpu(a, 50, fmt=ofl.OFL_COEF_BF16_OFFSET)
     pe, ge = check_against_oracle(a, g, gosa, 50, tol_p=TOL_BF16, tol_g=TOL_BF16, ref=ref)
     say(f"  vs FP32-input oracle: p rel {pe:.2e} gosa rel {ge:.2e}")
+    # the library's bias (its own encoder) must be the oracle's, which decodes the reference
     bias = ofl.ofl_grid_coef_bias(g.handle)
     dec = dict(a)
     for n, name in enumerate(ofl.COEF_NAMES):
-        dec[name] = oracle.offset_bf16_decode(a[name], bias[n])
+        ref_bias = oracle.offset_bias(a[name])
+        assert bias[n] == ref_bias, name
+        dec[name] = oracle.offset_bf16_decode(a[name], ref_bias)
     pe2, ge2 = check_against_oracle(dec, g, gosa, 50)
     say(f"  vs decoded-input oracle: p rel {pe2:.2e} gosa rel {ge2:.2e}")
     g.close()

@@ -103,6 +103,29 @@ def test_device_bytes_follow_the_row_alignment():
         assert e.value.code == ofl.OFL_EINVAL and "row_align" in ofl.ofl_last_error()
 
 
+def test_library_bias_equals_the_oracle_bias():
+    """The library's bfloat16-offset encoder (C++, at grid creation) and the
+    oracle's offset_bias are two independent derivations of the bias: they
+    must agree exactly on every array of a seeded problem, and on arrays that
+    tell the mid-range from the mean and from zero."""
+    a = synth.make_problem(19, 11, 9, seed=3)
+    rng = np.random.default_rng(11)
+    n = a["a0"].size
+    e = 2.0 ** -20
+    a["a1"] = (0.95 + 0.1 * rng.uniform(0, 1, n) ** 6).astype(np.float32).reshape(a["a1"].shape)
+    a["wrk1"] = np.where(rng.uniform(0, 1, n) < 0.5, 0.5, -3.0).astype(np.float32).reshape(a["wrk1"].shape)
+    b0 = np.full(n, 1 + e, np.float32)
+    b0[-1] = 1.5 + e
+    a["b0"] = b0.reshape(a["b0"].shape)
+    g = ofl.Grid(a, coef_format=ofl.OFL_COEF_BF16_OFFSET)
+    lib_bias = ofl.ofl_grid_coef_bias(g.handle)
+    for k, name in enumerate(ofl.COEF_NAMES):
+        assert lib_bias[k] == oracle.offset_bias(a[name]), name
+    assert lib_bias[ofl.COEF_NAMES.index("b0")] == np.float32(1 + e + 0.25)
+    assert lib_bias[ofl.COEF_NAMES.index("wrk1")] == 0.0
+    g.close()
+
+
 def test_fused_residual_refused_for_compensated_sums():
     """The fused residual sums in FP64 only: a grid that asks for the
     compensated FP32 sum cannot have it fused (a copy-back exchange alone is fine)."""

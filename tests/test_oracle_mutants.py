@@ -6,6 +6,7 @@ import shutil
 import subprocess
 import tempfile
 
+import numpy as np
 import pytest
 
 import oracle
@@ -60,6 +61,62 @@ PIN_CHECKS = [
     gpins.test_outer_product_and_transpose_identity,
     gpins.test_small_integer_products_against_brute_force,
 ]
+
+
+# Plausible mistakes in the offset-bfloat16 bias (oracle.offset_bias, the one
+# oracle function written in Python), planted by replacing the function.
+def _bias_mean(x):
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    if np.array_equal(oracle.bf16_rne(x), x):
+        return np.float32(0.0)
+    return np.float32(np.mean(x, dtype=np.float64))
+
+
+def _bias_no_exact_rule(x):
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    return np.float32(0.5 * (float(x.min()) + float(x.max())))
+
+
+def _bias_min(x):
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    if np.array_equal(oracle.bf16_rne(x), x):
+        return np.float32(0.0)
+    return np.float32(x.min())
+
+
+def _bias_exact_rule_inverted(x):
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    if not np.array_equal(oracle.bf16_rne(x), x):
+        return np.float32(0.0)
+    return np.float32(0.5 * (float(x.min()) + float(x.max())))
+
+
+BIAS_MUTANTS = [("bias is the mean", _bias_mean), ("bias without the exactness rule", _bias_no_exact_rule),
+                ("bias is the minimum", _bias_min), ("exactness rule inverted", _bias_exact_rule_inverted)]
+
+BIAS_PIN_CHECKS = [
+    pins.test_offset_bias_is_the_mid_range_not_the_mean,
+    pins.test_offset_bias_halves_the_range_of_a_skewed_draw,
+    pins.test_offset_bias_is_zero_for_bfloat16_exact_arrays,
+    pins.test_offset_encoding_rule,
+]
+
+
+def test_unmutated_bias_passes_every_check():
+    for check in BIAS_PIN_CHECKS:
+        check()
+
+
+@pytest.mark.parametrize("name,fn", BIAS_MUTANTS, ids=[m[0] for m in BIAS_MUTANTS])
+def test_pins_catch_bias_mutant(monkeypatch, name, fn):
+    monkeypatch.setattr(oracle, "offset_bias", fn)
+    caught = []
+    for n, check in enumerate(BIAS_PIN_CHECKS):
+        try:
+            check()
+        except AssertionError:
+            caught.append(n)
+    assert caught, f"no pin caught mutant {name!r}"
 
 
 @pytest.fixture(scope="module")

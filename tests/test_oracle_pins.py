@@ -409,6 +409,40 @@ def test_offset_encoding_rule():
     assert err_plain > 8 * err_off
 
 
+def test_offset_bias_is_the_mid_range_not_the_mean():
+    """Hand-worked: [1+e, 1+e, 1+e, 1.5+e] with e = 2^-20 (not bfloat16-exact)
+    has mid-range 1.25+e and mean 1.125+e; the bias is the mid-range, exactly
+    (1.25+e is an FP32 value)."""
+    e = 2.0 ** -20
+    x = np.array([1 + e, 1 + e, 1 + e, 1.5 + e], np.float32)
+    assert oracle.offset_bias(x) == np.float32(1.25 + e)
+    # one value off the bfloat16 grid is enough: [-3, 0.5, 1, 1.5+e] -> -0.75 + e/2
+    x = np.array([1.0, 0.5, -3.0, 1.5 + e], np.float32)
+    assert oracle.offset_bias(x) == np.float32(-0.75 + e / 2)
+
+
+def test_offset_bias_halves_the_range_of_a_skewed_draw():
+    """The mid-range is the one bias that makes max|x - bias| half the range;
+    on a draw crowded at the bottom of [0.95, 1.05] (mean about 0.964) any
+    other centre, the mean among them, leaves some value farther away."""
+    rng = np.random.default_rng(7)
+    x = (0.95 + 0.1 * rng.uniform(0, 1, 4096) ** 6).astype(np.float32)
+    b = float(oracle.offset_bias(x))
+    lo, hi = float(x.min()), float(x.max())
+    half = (hi - lo) / 2
+    dev = np.max(np.abs(x.astype(np.float64) - b))
+    assert dev <= half + 2.0 ** -24 and dev >= half - 2.0 ** -24
+    assert abs(b - float(x.mean(dtype=np.float64))) > 0.03
+
+
+def test_offset_bias_is_zero_for_bfloat16_exact_arrays():
+    """Every value already on the bfloat16 grid: no bias (the encoding is then
+    exact), whatever the range."""
+    x = np.array([1.0, 0.5, -3.0, 1.5, 2.0 ** -10, 96.0], np.float32)
+    assert oracle.offset_bias(x) == 0.0
+    assert oracle.offset_bias(np.full(10, 0.25, np.float32)) == 0.0
+
+
 # ------------------------------------------------------- generator contract
 
 
