@@ -46,6 +46,8 @@ def _load():
         lib.oracle_bf16_rne_array.restype = None
         lib.oracle_gemm.argtypes = [ctypes.c_int] * 3 + [_DP, ctypes.c_int, _DP, ctypes.c_int, _DP, ctypes.c_int]
         lib.oracle_gemm.restype = ctypes.c_int
+        lib.oracle_threads.argtypes = []
+        lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -61,6 +63,12 @@ def use_library(path):
         yield
     finally:
         _lib, _lib_path = saved
+
+
+def threads():
+    """Host threads the loaded oracle build uses (1, or the OpenMP thread count
+    when loaded from the all-cores build through use_library)."""
+    return int(_load().oracle_threads())
 
 
 def _f64(a):

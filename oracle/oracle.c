@@ -31,8 +31,16 @@
  * from the old p before any point of p changes.
  *
  * Arithmetic: FP64 throughout, inputs widened exactly from what the caller
- * stores. The residual is accumulated sequentially in k, then j, then i order.
- * Build with -ffp-contract=off so that no multiply-add is fused.
+ * stores. The residual is a plain sum over the interior in a fixed order: each
+ * k-plane's squares are added in j, then i order, and the plane sums are then
+ * added in k order. Build with -ffp-contract=off so that no multiply-add is
+ * fused.
+ *
+ * The loops over k carry OpenMP directives. The plain build ignores them; a
+ * build with -fopenmp runs the planes on all host cores, which is how the
+ * oracle is timed on every core. Each plane is still computed by one thread in
+ * the same order and the plane sums are added in k order afterwards, so both
+ * builds give bit-identical results.
  *
  * Layout: linear index of (i,j,k) is i + I*(j + J*k), i fastest.
  * Coefficient order: a0 a1 a2 a3 b0 b1 b2 c0 c1 c2 bnd wrk1.
@@ -43,6 +51,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 enum { A0, A1, A2, A3, B0, B1, B2, C0, C1, C2, BND, WRK1, NCOEF };
 
@@ -84,21 +95,37 @@ static double ss_at(int I, int J, const double *const co[ORACLE_NCOEF], const do
     return (co[A3][c] * s0 - p[c]) * co[BND][c];
 }
 
+/* Sum of plane[0..n) in index order (the residual's plane sums, k order). */
+static double sum_planes(const double *plane, int n)
+{
+    double sum = 0.0;
+    for (int t = 0; t < n; ++t)
+        sum += plane[t];
+    return sum;
+}
+
 int oracle_sweep(int I, int J, int K, const double *const co[ORACLE_NCOEF], const double *p, double omega,
                  double *wrk2, double *gosa)
 {
     if (!dims_ok(I, J, K) || !coefs_ok(co) || !p || !wrk2)
         return -1;
-    double sum = 0.0;
-    for (int k = 1; k < K - 1; ++k)
+    double *plane = (double *)calloc((size_t)(K - 2), sizeof(double));
+    if (!plane)
+        return -2;
+#pragma omp parallel for schedule(static)
+    for (int k = 1; k < K - 1; ++k) {
+        double sum = 0.0;
         for (int j = 1; j < J - 1; ++j)
             for (int i = 1; i < I - 1; ++i) {
                 double ss = ss_at(I, J, co, p, i, j, k);
                 AT(wrk2, i, j, k) = AT(p, i, j, k) + omega * ss;
                 sum += ss * ss;
             }
+        plane[k - 1] = sum;
+    }
     if (gosa)
-        *gosa = sum;
+        *gosa = sum_planes(plane, K - 2);
+    free(plane);
     return 0;
 }
 
@@ -106,14 +133,21 @@ int oracle_residual(int I, int J, int K, const double *const co[ORACLE_NCOEF], c
 {
     if (!dims_ok(I, J, K) || !coefs_ok(co) || !p || !gosa)
         return -1;
-    double sum = 0.0;
-    for (int k = 1; k < K - 1; ++k)
+    double *plane = (double *)calloc((size_t)(K - 2), sizeof(double));
+    if (!plane)
+        return -2;
+#pragma omp parallel for schedule(static)
+    for (int k = 1; k < K - 1; ++k) {
+        double sum = 0.0;
         for (int j = 1; j < J - 1; ++j)
             for (int i = 1; i < I - 1; ++i) {
                 double ss = ss_at(I, J, co, p, i, j, k);
                 sum += ss * ss;
             }
-    *gosa = sum;
+        plane[k - 1] = sum;
+    }
+    *gosa = sum_planes(plane, K - 2);
+    free(plane);
     return 0;
 }
 
@@ -129,8 +163,12 @@ int oracle_jacobi(int I, int J, int K, const double *const co[ORACLE_NCOEF], dou
     double last = NAN;
     for (int it = 0; it < iters; ++it) {
         /* nests S and R: new values from the old iterate, residual of the old iterate */
-        oracle_sweep(I, J, K, co, p, omega, wrk2, &last);
+        if (oracle_sweep(I, J, K, co, p, omega, wrk2, &last) != 0) {
+            free(wrk2);
+            return -2;
+        }
         /* nest C: copy back on the interior only */
+#pragma omp parallel for schedule(static)
         for (int k = 1; k < K - 1; ++k)
             for (int j = 1; j < J - 1; ++j)
                 for (int i = 1; i < I - 1; ++i)
@@ -139,6 +177,15 @@ int oracle_jacobi(int I, int J, int K, const double *const co[ORACLE_NCOEF], dou
     free(wrk2);
     *gosa = last;
     return 0;
+}
+
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /*

@@ -32,6 +32,10 @@ int oracle_residual(int I, int J, int K, const double *const co[ORACLE_NCOEF], c
 int oracle_jacobi(int I, int J, int K, const double *const co[ORACLE_NCOEF], double *p, double omega, int iters,
                   double *gosa);
 
+/* Host threads the loops over k use: 1 for the plain build, the OpenMP
+ * thread count for a build with -fopenmp (both give bit-identical results). */
+int oracle_threads(void);
+
 /* FP32 -> nearest bfloat16 (ties to even) -> FP32. */
 float oracle_bf16_rne(float x);
 void oracle_bf16_rne_array(const float *in, float *out, size_t n);

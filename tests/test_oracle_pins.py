@@ -409,6 +409,26 @@ def test_offset_encoding_rule():
     assert err_plain > 8 * err_off
 
 
+def test_all_cores_build_is_bit_identical():
+    """The same oracle.c built with -fopenmp (the all-cores CPU baseline) runs
+    the planes on several threads; each plane is still summed in j, i order
+    and the plane sums in k order, so p and the residual are bit-identical to
+    the single-thread build's."""
+    import oracle.build as ob
+
+    if not os.path.exists(ob.LIB_OMP):
+        ob.build()
+    a = synth.make_problem(37, 29, 41, seed=23)
+    p1, g1 = oracle.jacobi(a, 6, 0.8)
+    r1 = oracle.residual(dict(a, p=p1))
+    with oracle.use_library(ob.LIB_OMP):
+        threads = oracle.threads()
+        p2, g2 = oracle.jacobi(a, 6, 0.8)
+        r2 = oracle.residual(dict(a, p=p2))
+    assert oracle.threads() == 1 and threads >= 1
+    assert np.array_equal(p1, p2) and g1 == g2 and r1 == r2
+
+
 def test_offset_bias_is_the_mid_range_not_the_mean():
     """Hand-worked: [1+e, 1+e, 1+e, 1.5+e] with e = 2^-20 (not bfloat16-exact)
     has mid-range 1.25+e and mean 1.125+e; the bias is the mid-range, exactly
