@@ -8,10 +8,13 @@ value = lattice updates per second of the whole iteration, in GLUP/s.
 
 Also reported: the sweep kernel against the HBM roofline (HIP-event time of
 every sweep launch inside the timed region, and the counter-measured bytes when
-they were taken on the current kernel source), the streaming ceiling of a 1 GiB
-copy, the bfloat16-offset, fused and batched forms of the same metric (batches
-with the library's default batch tile, or GA-tuned ones with --tune-batch), and
-the FP64 oracle timed on a bounded sample on the host cores.
+they were taken on the current kernel source) and against the practical
+ceiling of its own streaming pattern (13 reads + 1 write per point without the
+stencil), a 1:1 copy's rate, the bfloat16-offset, fused and batched forms of
+the same metric (batches with the library's default batch tile, or GA-tuned
+ones with --tune-batch), every form's error against the FP64 oracle over the
+oracle's sample, and the FP64 oracle timed on that bounded sample (the first
+50 iterations) on one host thread and on all host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-variants]
        [--skip-cpu-baseline] [--tune-batch] [--profile-only NAME]
@@ -67,6 +70,32 @@ def measured_traffic(tile):
     if rec.get("kernel_source_sha256_16") != kernel_hash() or rec.get("tile") != tile:
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def errors_against(p, gosa, p_ref, g_ref):
+    """Relative errors of a result against the FP64 oracle: p as the max-norm
+    over the interior (also the L2 norm), the residual as |d| / |ref|."""
+    inner = (slice(1, -1),) * 3
+    d = np.asarray(p, np.float64)[inner] - p_ref[inner]
+    return {"p_max_rel_err": float(np.max(np.abs(d)) / np.max(np.abs(p_ref[inner]))),
+            "p_l2_rel_err": float(np.linalg.norm(d) / np.linalg.norm(p_ref[inner])),
+            "gosa_rel_err": float(abs(gosa - g_ref) / abs(g_ref))}
+
+
+def single_error(ofl, arrays, fmt, fusion, iters, p_ref, g_ref):
+    """One form on a fresh grid for ``iters`` iterations from the initial
+    iterate, in the benchmark's configuration, against the oracle's result."""
+    g = ofl.Grid(arrays, coef_format=fmt, torch_memory=True)
+    if fusion:
+        ofl.ofl_set_fusion(g.handle, fusion)
+    ofl.ofl_set_offload_mask(g.handle, ofl.OFL_MASK_ALL_GPU, ofl.OFL_XFER_HOISTED)
+    ofl.ofl_data_enter(g.handle)
+    gosa = ofl.ofl_jacobi_run(g.handle, iters, OMEGA)
+    ofl.ofl_data_exit(g.handle)
+    e = errors_against(g.p, gosa, p_ref, g_ref)
+    g.close()
+    e["iterations"] = iters
+    return e
 
 
 def run_single(ofl, arrays, fmt, steps, warmup, tile=None, profile=True, iters=ITERS, fusion=0):
@@ -134,26 +163,44 @@ def run_single(ofl, arrays, fmt, steps, warmup, tile=None, profile=True, iters=I
     return res
 
 
-def run_batch(ofl, probs, fmt, steps, warmup, tune, iters=ITERS, row_align=0):
+def run_batch(ofl, probs, fmt, steps, warmup, tune, iters=ITERS, row_align=0, check=None):
     """The uneven grids in one batch: plain and fused graph runs against the
     same grids run one after another with single-grid calls. ``row_align``:
-    the grids' device row alignment (4: packed rows in the batch)."""
+    the grids' device row alignment (4: packed rows in the batch). ``check``:
+    (iterations, {grid index: oracle (p, gosa)}); each form's first run is
+    that many iterations from the initial iterate, and its worst error on
+    those grids against the oracle is reported."""
     import torch
 
     n_grids = len(probs)
     total_lups = sum(interior(*shape) for shape, _ in probs) * iters
-    grids = [ofl.Grid(arr, coef_format=fmt, row_align=row_align) for _, arr in probs]
-    for g in grids:
-        ofl.ofl_data_enter(g.handle)
-    b = ofl.ofl_batch_create([g.handle for g in grids])
-    tuned = None
-    if tune:
-        log("GA tile search for the batch")
-        r = ofl.ofl_batch_tune(b, ofl.ga_params(population=10, generations=6, probe_iters=10, repeats=2))
-        tuned = {"tile": r.best.as_dict(), "probe_ms": r.best_ms, "evaluated": r.evaluated, "rejected": r.rejected}
 
-    def timed(fusion):
-        ofl.ofl_batch_set_fusion(b, fusion)
+    def setup():
+        grids = [ofl.Grid(arr, coef_format=fmt, row_align=row_align) for _, arr in probs]
+        for g in grids:
+            ofl.ofl_data_enter(g.handle)
+        return grids, ofl.ofl_batch_create([g.handle for g in grids])
+
+    def teardown(grids, b):
+        ofl.ofl_batch_destroy(b)
+        for g in grids:
+            ofl.ofl_data_exit(g.handle)
+            g.close()
+
+    def oracle_error(grids, b):
+        if not check:
+            return None
+        n_it, refs = check
+        gosa = ofl.ofl_batch_run(b, n_it, OMEGA, n_grids)
+        worst = {"p_max_rel_err": 0.0, "gosa_rel_err": 0.0}
+        for t, (p_ref, g_ref) in refs.items():
+            ofl.ofl_update_host(grids[t].handle)
+            e = errors_against(grids[t].p, gosa[t], p_ref, g_ref)
+            worst = {k: max(worst[k], e[k]) for k in worst}
+        worst.update(iterations=n_it, grids=sorted(refs))
+        return worst
+
+    def timed(b):
         for _ in range(warmup):
             ofl.ofl_batch_run(b, iters, OMEGA, n_grids)
         torch.cuda.synchronize()
@@ -163,8 +210,15 @@ def run_batch(ofl, probs, fmt, steps, warmup, tune, iters=ITERS, row_align=0):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
-    dt_batch = timed(0)
-    dt_fused = timed(ofl.OFL_FUSE_RESIDUAL | ofl.OFL_FUSE_COPYBACK_SWAP)
+    tuned = None
+    errors = {}
+    grids, b = setup()
+    if tune:
+        log("GA tile search for the batch")
+        r = ofl.ofl_batch_tune(b, ofl.ga_params(population=10, generations=6, probe_iters=10, repeats=2))
+        tuned = {"tile": r.best.as_dict(), "probe_ms": r.best_ms, "evaluated": r.evaluated, "rejected": r.rejected}
+    errors["plain"] = oracle_error(grids, b)
+    dt_batch = timed(b)
     tile_used = ofl.ofl_batch_get_tile(b).as_dict()
     ofl.ofl_batch_destroy(b)
     # baseline: the same grids one after another, plain single-grid runs
@@ -179,6 +233,14 @@ def run_batch(ofl, probs, fmt, steps, warmup, tune, iters=ITERS, row_align=0):
     for g in grids:
         ofl.ofl_data_exit(g.handle)
         g.close()
+    # the fused form on fresh grids, so that its check starts from the initial iterate
+    grids, b = setup()
+    if tuned:
+        ofl.ofl_batch_set_tile(b, ofl.tile(**tuned["tile"]))
+    ofl.ofl_batch_set_fusion(b, ofl.OFL_FUSE_RESIDUAL | ofl.OFL_FUSE_COPYBACK_SWAP)
+    errors["fused"] = oracle_error(grids, b)
+    dt_fused = timed(b)
+    teardown(grids, b)
     return {
         "grids": n_grids,
         "lattice_updates": total_lups,
@@ -191,6 +253,8 @@ def run_batch(ofl, probs, fmt, steps, warmup, tune, iters=ITERS, row_align=0):
         "tile": tile_used,
         "row_align": row_align,
         "tuner": tuned,
+        "oracle_error": errors["plain"],
+        "oracle_error_fused": errors["fused"],
     }
 
 
@@ -521,8 +585,8 @@ def host_info():
     return {"cpu_model": model, "logical_cpus": os.cpu_count(), "cpus_available": len(os.sched_getaffinity(0))}
 
 
-def copy_ceiling(ofl, reps=5):
-    """The library's copy kernel on 1 GiB: the streaming ceiling of a read + write pattern (GB/s moved)."""
+def copy_rate(ofl, reps=5):
+    """The library's copy kernel on 1 GiB: the rate of a 1:1 read + write stream (GB/s moved)."""
     import torch
 
     nbytes = 1 << 30
@@ -538,27 +602,95 @@ def copy_ceiling(ofl, reps=5):
     torch.cuda.synchronize()
     gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del src, dst
-    return {"kernel": "copy_kernel, 1 GiB read + 1 GiB written", "gbs": round(gbs, 1),
-            "frac": round(gbs / PEAK_HBM_GBS, 4)}
+    return {"kernel": "copy_kernel, 1 GiB read + 1 GiB written (a 1:1 stream, not the sweep's pattern)",
+            "gbs": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)}
 
 
-def cpu_baseline(arrays, iters):
-    import oracle
+def pattern_ceilings(ofl, reps=5):
+    """The sweep's own streaming pattern without the stencil (ofl_device_stream):
+    13 FP32 reads + 1 FP32 write per point, and 1 FP32 + 12 bfloat16 reads + 1
+    FP32 write, each over as many points as the headline grid's interior, 14
+    separate arrays, linear order. GB/s of the pattern's bytes."""
+    import torch
 
-    log(f"oracle: {iters} iterations of 257x257x513 in FP64 on the host")
-    t0 = time.perf_counter()
-    oracle.jacobi(arrays, iters, float(OMEGA))
-    dt = time.perf_counter() - t0
     I, J, K = SHAPE
-    return {
-        "value": interior(I, J, K) * iters / dt / 1e9,
+    n = (interior(I, J, K) + 3) // 4 * 4
+    out = {}
+    s = torch.cuda.current_stream()
+    for name, n32, n16, bpp in (("f32", 13, 0, 56), ("bf16", 1, 12, 32)):
+        f = [torch.ones(n, dtype=torch.float32, device="cuda") for _ in range(n32)]
+        h = [torch.ones(n, dtype=torch.bfloat16, device="cuda") for _ in range(n16)]
+        dst = torch.empty(n, dtype=torch.float32, device="cuda")
+        args = ([x.data_ptr() for x in f], [x.data_ptr() for x in h], dst.data_ptr(), n, s.cuda_stream)
+        ofl.ofl_device_stream(*args)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            ofl.ofl_device_stream(*args)
+        e1.record(s)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        gbs = bpp * n / (us * 1e-6) / 1e9
+        out[name] = {"sources": f"{n32} FP32 + {n16} bfloat16, 1 FP32 written", "bytes_per_point": bpp,
+                     "points": n, "avg_launch_us": round(us, 2), "gbs": round(gbs, 1),
+                     "frac": round(gbs / PEAK_HBM_GBS, 4)}
+        del f, h, dst
+    return out
+
+
+def widened(arrays):
+    """The inputs in FP64, made before any oracle timing starts."""
+    return {k: np.ascontiguousarray(v, dtype=np.float64) for k, v in arrays.items()}
+
+
+def cpu_baseline(arrays64, iters):
+    """The FP64 oracle timed around its iteration loop (the inputs are widened
+    beforehand): the single-thread build, and the same oracle.c built with
+    OpenMP over k on every host core the run may use. Both give bit-identical
+    results (checked here); the all-cores figure is the baseline, the
+    single-thread one rides along. Returns (record, (p_ref, gosa_ref))."""
+    import oracle
+    import oracle.build as ob
+
+    I, J, K = SHAPE
+    lups = interior(I, J, K) * iters
+    log(f"oracle: {iters} iterations of 257x257x513 in FP64, one host thread")
+    t0 = time.perf_counter()
+    p_ref, g_ref = oracle.jacobi(arrays64, iters, float(OMEGA))
+    dt1 = time.perf_counter() - t0
+    if not os.path.exists(ob.LIB_OMP):
+        ob.build()
+    with oracle.use_library(ob.LIB_OMP):
+        threads = oracle.threads()
+        log(f"oracle: {iters} iterations of 257x257x513 in FP64, {threads} host threads")
+        t0 = time.perf_counter()
+        p_all, g_all = oracle.jacobi(arrays64, iters, float(OMEGA))
+        dtn = time.perf_counter() - t0
+    same = bool(np.array_equal(p_all, p_ref) and g_all == g_ref)
+    del p_all
+    rec = {
+        "value": lups / dtn / 1e9,
         "unit": "GLUP/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"257x257x513 grid, {iters} of the {ITERS} iterations, plain C FP64 oracle, one thread, "
-                  f"{dt:.1f} s including the FP32->FP64 widening of the inputs",
+        "sample": f"257x257x513 grid, {iters} of the {ITERS} iterations, plain C FP64 oracle built with OpenMP over "
+                  f"k, {threads} threads, {dtn:.2f} s around the iteration loop (inputs widened to FP64 beforehand)",
+        "bit_identical_to_single_thread": same,
+        "single_thread": {"value": lups / dt1 / 1e9, "unit": "GLUP/s", "cores": 1, "seconds": round(dt1, 2)},
         "host": host_info(),
     }
+    return rec, (p_ref, g_ref)
+
+
+def batch_check_refs(probs, iters):
+    """Oracle results for four fixed grids of the batch (the smallest, the
+    largest and the two around the median interior size), ``iters`` iterations."""
+    import oracle
+
+    order = sorted(range(len(probs)), key=lambda t: interior(*probs[t][0]))
+    pick = sorted({order[0], order[len(order) // 2 - 1], order[len(order) // 2], order[-1]})
+    log(f"oracle: {iters} iterations of batch grids {pick}")
+    return {t: oracle.jacobi(probs[t][1], iters, float(OMEGA)) for t in pick}
 
 
 def main():
@@ -697,8 +829,13 @@ def main():
         },
         "hbm_gbs_iteration": round(head["glups"] * ITER_BYTES["f32"], 1),
         "roofline": roofline,
-        "stream_copy_ceiling": copy_ceiling(ofl),
     }
+    log("streaming ceilings: the sweep's pattern without the stencil, and a 1:1 copy")
+    ceil = pattern_ceilings(ofl)
+    out["sweep_pattern_ceiling"] = ceil
+    out["copy_1to1"] = copy_rate(ofl)
+    roofline["pattern_ceiling_gbs"] = ceil["f32"]["gbs"]
+    roofline["frac_of_pattern_ceiling"] = round(achieved / ceil["f32"]["gbs"], 4)
     if not args.skip_variants:
         log("bf16-offset variant")
         bf = run_single(ofl, arrays, ofl.OFL_COEF_BF16_OFFSET, args.steps, args.warmup)
@@ -711,8 +848,12 @@ def main():
                 "sweep_avg_us": round(bf_sweep_us, 2),
                 "sweep_achieved_gbs": round(SWEEP_BYTES["bf16"] * lup_launch / (bf_sweep_us * 1e-6) / 1e9, 1),
                 "speedup_vs_f32": round(bf["glups"] / head["glups"], 3),
+                "tile": bf["tile"],
             }
         }
+        bf_gbs = out["variants"]["bf16_offset"]["sweep_achieved_gbs"]
+        out["variants"]["bf16_offset"]["sweep_frac_of_hbm_peak"] = round(bf_gbs / PEAK_HBM_GBS, 4)
+        out["variants"]["bf16_offset"]["sweep_frac_of_pattern_ceiling"] = round(bf_gbs / ceil["bf16"]["gbs"], 4)
         if args.tune:
             for name, fmt in (("ga_tuned_f32", ofl.OFL_COEF_F32), ("ga_tuned_bf16_offset", ofl.OFL_COEF_BF16_OFFSET)):
                 best, info = tune_headline(ofl, arrays, fmt)
@@ -731,16 +872,35 @@ def main():
                 "sweep_avg_us": round(fr["nest_ms_avg"][0] * 1e3, 2),
                 "speedup_vs_f32": round(fr["glups"] / head["glups"], 3),
             }
-        if not args.skip_batch:
-            log(f"generating {args.batch_grids} uneven grids")
-            probs = synth.make_batch(args.batch_grids)
-            for name, fmt in (("batched_f32", ofl.OFL_COEF_F32), ("batched_bf16_offset", ofl.OFL_COEF_BF16_OFFSET)):
-                log(f"{name} variant")
-                out["variants"][name] = run_batch(ofl, probs, fmt, max(1, args.steps // 2), 1, args.tune_batch,
-                                                  row_align=args.batch_row_align)
-            del probs
     if not args.skip_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(arrays, args.oracle_iters)
+        # the oracle on a bounded sample (the first oracle_iters iterations),
+        # and every single-grid form's error against it over the same iterations
+        arrays64 = widened(arrays)
+        out["cpu_baseline"], (p_ref, g_ref) = cpu_baseline(arrays64, args.oracle_iters)
+        del arrays64
+        fuse = ofl.OFL_FUSE_RESIDUAL | ofl.OFL_FUSE_COPYBACK_SWAP
+        forms = [(None, ofl.OFL_COEF_F32, 0)]
+        if not args.skip_variants:
+            forms += [("bf16_offset", ofl.OFL_COEF_BF16_OFFSET, 0), ("fused_f32", ofl.OFL_COEF_F32, fuse),
+                      ("fused_bf16_offset", ofl.OFL_COEF_BF16_OFFSET, fuse)]
+        for name, fmt, fusion in forms:
+            log(f"error against the oracle: {name or 'FP32 headline'}, {args.oracle_iters} iterations")
+            e = single_error(ofl, arrays, fmt, fusion, args.oracle_iters, p_ref, g_ref)
+            if name is None:
+                out["oracle_error"] = e
+            else:
+                out["variants"][name]["oracle_error"] = e
+        del p_ref
+    if not args.skip_variants and not args.skip_batch:
+        log(f"generating {args.batch_grids} uneven grids")
+        probs = synth.make_batch(args.batch_grids)
+        check = None if args.skip_cpu_baseline else (args.oracle_iters, batch_check_refs(probs, args.oracle_iters))
+        for name, fmt in (("batched_f32", ofl.OFL_COEF_F32), ("batched_bf16_offset", ofl.OFL_COEF_BF16_OFFSET)):
+            log(f"{name} variant")
+            out["variants"][name] = run_batch(ofl, probs, fmt, max(1, args.steps // 2), 1, args.tune_batch,
+                                              row_align=args.batch_row_align, check=check)
+        del probs
+    if not args.skip_cpu_baseline:
         out["cpu_program"] = cpu_program(ofl, arrays, args.oracle_iters)
     print(json.dumps(out), flush=True)
 

@@ -493,8 +493,21 @@ int ofl_gemm_f32(int M, int N, int K, const float *A, int lda, const float *B, i
 /* ---- measurement helper ---------------------------------------------------- */
 /* Device-to-device copy of bytes (multiple of 16, 16-byte aligned pointers)
  * with the library's streaming copy kernel on the given stream (NULL = the
- * default stream): the practical HBM ceiling the sweep is compared with. */
+ * default stream): the rate of a 1:1 read + write stream. */
 int ofl_device_copy(void *dst, const void *src, size_t bytes, void *stream);
+
+/* The sweep's streaming pattern without the stencil, as a ceiling to compare
+ * the sweep with: dst[t] = sum over the n32 FP32 sources src32[s][t] plus
+ * sum over the n16 bfloat16 sources src16[s][t] (widened), for t < n. Every
+ * array is a separate contiguous device array, read with non-temporal loads of
+ * 4 elements per lane in linear order, dst written the same way; queued on
+ * stream (NULL: the default stream). (n32, n16) must be (13, 0), the FP32
+ * sweep's 13 reads and 1 write per point (56 bytes), or (1, 12), the bfloat16
+ * sweep's (32 bytes); other counts give ENOTSUP. EINVAL for NULL pointers, n
+ * not a multiple of 4, or sources/dst not aligned to their vector (16 bytes
+ * for FP32, 8 for bfloat16). */
+int ofl_device_stream(const float *const *src32, int n32, const uint16_t *const *src16, int n16, float *dst,
+                      size_t n, void *stream);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *ofl_last_error(void);

@@ -178,6 +178,8 @@ _SIGS = {
     "ofl_gemm_f32": ([ctypes.c_int] * 3 + [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                                            ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "ofl_device_copy": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+    "ofl_device_stream": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
+                           ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
     "ofl_last_error": ([], ctypes.c_char_p),
     "ofl_version": ([], ctypes.c_char_p),
 }
@@ -447,6 +449,14 @@ def ofl_gemm_f32(M: int, N: int, K: int, a_ptr: int, lda: int, b_ptr: int, ldb: 
 
 def ofl_device_copy(dst_ptr: int, src_ptr: int, nbytes: int, stream: Optional[int] = None) -> None:
     _check(lib().ofl_device_copy(dst_ptr, src_ptr, nbytes, stream))
+
+
+def ofl_device_stream(src32_ptrs: Sequence[int], src16_ptrs: Sequence[int], dst_ptr: int, n: int,
+                      stream: Optional[int] = None) -> None:
+    """The sweep's streaming pattern on device arrays: dst = sum of the FP32 and bfloat16 sources."""
+    s32 = (ctypes.c_void_p * max(1, len(src32_ptrs)))(*src32_ptrs)
+    s16 = (ctypes.c_void_p * max(1, len(src16_ptrs)))(*src16_ptrs)
+    _check(lib().ofl_device_stream(s32, len(src32_ptrs), s16, len(src16_ptrs), dst_ptr, n, stream))
 
 
 def tile(vec=4, rows=4, kchunk=32, flags=0, occupancy=0) -> OflTile:

@@ -1278,4 +1278,23 @@ int ofl_device_copy(void *dst, const void *src, size_t bytes, void *stream) {
     });
 }
 
+int ofl_device_stream(const float *const *src32, int n32, const uint16_t *const *src16, int n16, float *dst,
+                      size_t n, void *stream) {
+    return guarded(nullptr, [&] {
+        if (!dst || (n32 > 0 && !src32) || (n16 > 0 && !src16))
+            fail(OFL_EINVAL, "NULL pointer");
+        if (!((n32 == 13 && n16 == 0) || (n32 == 1 && n16 == 12)))
+            fail(OFL_ENOTSUP, "stream patterns: 13 FP32 sources, or 1 FP32 and 12 bfloat16 sources");
+        if (n % 4 != 0 || reinterpret_cast<uintptr_t>(dst) % 16 != 0)
+            fail(OFL_EINVAL, "n must be a multiple of 4 and dst 16-byte aligned");
+        for (int t = 0; t < n32; ++t)
+            if (!src32[t] || reinterpret_cast<uintptr_t>(src32[t]) % 16 != 0)
+                fail(OFL_EINVAL, "every FP32 source must be given and 16-byte aligned");
+        for (int t = 0; t < n16; ++t)
+            if (!src16[t] || reinterpret_cast<uintptr_t>(src16[t]) % 8 != 0)
+                fail(OFL_EINVAL, "every bfloat16 source must be given and 8-byte aligned");
+        launch_stream(src32, n32, src16, n16, dst, n, static_cast<hipStream_t>(stream));
+    });
+}
+
 }  // extern "C"

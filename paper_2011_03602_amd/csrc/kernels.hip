@@ -786,6 +786,46 @@ __global__ __launch_bounds__(256) void copy_kernel(const u4 *__restrict__ src, u
         dst[t] = src[t];
 }
 
+// The sweep's access pattern without the stencil: every lane reads 4
+// consecutive elements of each of N32 FP32 streams and N16 bfloat16 streams
+// (non-temporal, linear order) and writes their sum to one FP32 stream. With
+// (13, 0) that is the FP32 sweep's 13 reads and 1 write per point, with
+// (1, 12) the bfloat16 sweep's; the rate it reaches is the practical HBM
+// ceiling of that pattern. One vector per lane and many work-groups, as in the
+// sweep.
+struct StreamArgs {
+    const float *f[16];
+    const uint16_t *h[16];
+    float *dst;
+};
+
+template <int N32, int N16>
+__global__ __launch_bounds__(256) void stream_kernel(StreamArgs a, long long nvec) {
+    const long long v = blockIdx.x * 256LL + threadIdx.x;
+    if (v >= nvec)
+        return;
+    f4 x[N32];
+    u2 h[N16 > 0 ? N16 : 1];
+#pragma unroll
+    for (int s = 0; s < N32; ++s)
+        x[s] = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(a.f[s]) + v);
+#pragma unroll
+    for (int s = 0; s < N16; ++s)
+        h[s] = __builtin_nontemporal_load(reinterpret_cast<const u2 *>(a.h[s]) + v);
+    f4 acc = x[0];
+#pragma unroll
+    for (int s = 1; s < N32; ++s)
+        acc += x[s];
+#pragma unroll
+    for (int s = 0; s < N16; ++s) {
+        acc.x += bf16_lo(h[s].x);
+        acc.y += bf16_hi(h[s].x);
+        acc.z += bf16_lo(h[s].y);
+        acc.w += bf16_hi(h[s].y);
+    }
+    __builtin_nontemporal_store(acc, reinterpret_cast<f4 *>(a.dst) + v);
+}
+
 int grid_for(long long n, int threads, int cap) {
     long long b = (n + threads - 1) / threads;
     if (b < 1)
@@ -1057,6 +1097,29 @@ void launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s) {
         return;
     copy_kernel<<<grid_for(n, 256, 256 * 256), 256, 0, s>>>(static_cast<const u4 *>(src), static_cast<u4 *>(dst), n);
     check_launch("copy kernel launch");
+}
+
+void launch_stream(const float *const *src32, int n32, const uint16_t *const *src16, int n16, float *dst, size_t n,
+                   hipStream_t s) {
+    StreamArgs a{};
+    for (int t = 0; t < n32; ++t)
+        a.f[t] = src32[t];
+    for (int t = 0; t < n16; ++t)
+        a.h[t] = src16[t];
+    a.dst = dst;
+    const long long nvec = static_cast<long long>(n / 4);
+    if (nvec == 0)
+        return;
+    const long long blocks = (nvec + 255) / 256;
+    if (blocks > 0x7fffffffLL)
+        fail(OFL_EINVAL, "stream probe too large");
+    if (n32 == 13 && n16 == 0)
+        stream_kernel<13, 0><<<static_cast<int>(blocks), 256, 0, s>>>(a, nvec);
+    else if (n32 == 1 && n16 == 12)
+        stream_kernel<1, 12><<<static_cast<int>(blocks), 256, 0, s>>>(a, nvec);
+    else
+        fail(OFL_ENOTSUP, "stream probe patterns: 13 FP32 sources, or 1 FP32 and 12 bfloat16 sources");
+    check_launch("stream kernel launch");
 }
 
 int device_cu_count(int device) {

@@ -133,6 +133,10 @@ void launch_unpack(const void *arr, void *staging, int I, int J, int K, int pitc
                    hipStream_t s);
 void launch_fill_zero(void *ptr, size_t bytes, hipStream_t s);
 void launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+// dst[t] = sum of the n32 FP32 and n16 bfloat16 sources at t, t < n (n a
+// multiple of 4): the sweep's streaming pattern, (13, 0) or (1, 12).
+void launch_stream(const float *const *src32, int n32, const uint16_t *const *src16, int n16, float *dst, size_t n,
+                   hipStream_t s);
 
 // Batched launches (kernels.hip).
 // fused_parts != nullptr: fuse the residual, rows partials per item (slot item*rows + wave).

@@ -18,6 +18,9 @@ void launch_pack(const void *, void *, int, int, int, int, long long, int, hipSt
 void launch_unpack(const void *, void *, int, int, int, int, long long, int, hipStream_t) { no_device(); }
 void launch_fill_zero(void *, size_t, hipStream_t) { no_device(); }
 void launch_copy(void *, const void *, size_t, hipStream_t) { no_device(); }
+void launch_stream(const float *const *, int, const uint16_t *const *, int, float *, size_t, hipStream_t) {
+    no_device();
+}
 void launch_batch_sweep(const GridView *, const SweepItem *, int, const TileCfg &, int, float, int, hipStream_t,
                         double *) {
     no_device();

@@ -14,6 +14,7 @@ void launch_pack(const void *, void *, int, int, int, int, long long, int, hipSt
 void launch_unpack(const void *, void *, int, int, int, int, long long, int, hipStream_t) {}
 void launch_fill_zero(void *, size_t, hipStream_t) {}
 void launch_copy(void *, const void *, size_t, hipStream_t) {}
+void launch_stream(const float *const *, int, const uint16_t *const *, int, float *, size_t, hipStream_t) {}
 void launch_batch_sweep(const GridView *, const SweepItem *, int, const TileCfg &, int, float, int, hipStream_t,
                         double *) {}
 void launch_batch_finalize_parts(const GridView *, const double *, const long long *, int, float, hipStream_t) {}

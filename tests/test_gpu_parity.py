@@ -417,6 +417,25 @@ def test_device_copy_kernel():
     assert torch.equal(src, dst)
 
 
+@pytest.mark.parametrize("n32,n16", [(13, 0), (1, 12)])
+def test_device_stream_kernel(n32, n16):
+    """The sweep-pattern ceiling probe sums its sources exactly (small
+    integers, so any order is exact); n ends on a partial work-group."""
+    say("device stream", n32, n16)
+    n = 256 * 37 + 12
+    g = torch.Generator(device="cuda").manual_seed(n32)
+    f = [torch.randint(-64, 64, (n,), device="cuda", generator=g).float() for _ in range(n32)]
+    h = [torch.randint(-64, 64, (n,), device="cuda", generator=g).to(torch.bfloat16) for _ in range(n16)]
+    dst = torch.full((n,), float("nan"), device="cuda")
+    ofl.ofl_device_stream([x.data_ptr() for x in f], [x.data_ptr() for x in h], dst.data_ptr(), n)
+    torch.cuda.synchronize()
+    want = torch.stack(f).sum(0) + (torch.stack([x.float() for x in h]).sum(0) if h else 0)
+    assert torch.equal(dst, want)
+    with pytest.raises(ofl.OflError) as e:
+        ofl.ofl_device_stream([x.data_ptr() for x in f[:2]], [], dst.data_ptr(), n)
+    assert e.value.code == ofl.OFL_ENOTSUP
+
+
 # ------------------------------------------------------------------ fusion
 
 
