@@ -193,6 +193,23 @@ int ofl_get_regions(const ofl_grid *g, unsigned *mask, int level[3], int *xfer_m
  * or non-finite; EDEVICE when a GPU nest is requested and no GPU is usable. */
 int ofl_jacobi_run(ofl_grid *g, int iters, float omega, double *gosa_out);
 
+/* ofl_jacobi_run for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): it
+ * calls no hipMalloc, hipFree, event or graph creation. It runs the fused
+ * iteration (see ofl_set_fusion) with the sweep's per-wave residual partials in
+ * a library-owned device array of 2^19 FP64 slots (4 MiB per device, held
+ * until the process ends) instead of a buffer the library allocates; results
+ * are bitwise those of ofl_jacobi_run on the same grid and tile. Preconditions,
+ * each refused before any work: the grid is resident (ofl_data_enter done,
+ * ESTATE otherwise), gene 111 with hoisted transfers and whole nests (ENOTSUP),
+ * OFL_FUSE_RESIDUAL set (ENOTSUP), profiling off (ENOTSUP), not inside a batch
+ * (ESTATE), and a sweep of at most 2^19 waves for the grid's tile (EINVAL: a
+ * tile with longer k-chunks needs fewer). Every call on one
+ * device shares that array, so calls that overlap in time on one device (two
+ * host threads, or two streams) race and give wrong residuals; serialise them.
+ * p and gosa are as for ofl_jacobi_run; a data region stays open. */
+int ofl_jacobi_run_static(ofl_grid *g, int iters, float omega, double *gosa_out);
+
 /* Residual of the current iterate without changing it: S with omega = 1 into
  * wrk2, then R; no copy-back. Uses the devices of the current mask. The paper
  * defines no such call: it is the offloaded program's own residual nest, run

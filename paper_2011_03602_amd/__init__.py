@@ -140,6 +140,10 @@ _SIGS = {
     "ofl_get_regions": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint), ctypes.POINTER(ctypes.c_int),
                          ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "ofl_jacobi_run": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "ofl_jacobi_run_static": (
+        [ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.POINTER(ctypes.c_double)],
+        ctypes.c_int,
+    ),
     "ofl_residual": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "ofl_data_enter": ([ctypes.c_void_p], ctypes.c_int),
     "ofl_update_host": ([ctypes.c_void_p], ctypes.c_int),
@@ -260,6 +264,12 @@ def ofl_get_regions(g):
 def ofl_jacobi_run(g, iters: int, omega: float) -> float:
     gosa = ctypes.c_double()
     _check(lib().ofl_jacobi_run(g, iters, omega, ctypes.byref(gosa)))
+    return gosa.value
+
+
+def ofl_jacobi_run_static(g, iters: int, omega: float) -> float:
+    gosa = ctypes.c_double()
+    _check(lib().ofl_jacobi_run_static(g, iters, omega, ctypes.byref(gosa)))
     return gosa.value
 
 

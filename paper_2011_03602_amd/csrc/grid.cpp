@@ -467,12 +467,16 @@ namespace {
 // because wrk2's boundary was made equal to p's first and the sweep writes
 // outside the interior only p's own values. The three nests still count as
 // executed on the GPU.
-void run_fused(ofl_grid *g, int iters, float omega) {
+//
+// static_parts != nullptr: the per-wave partials go there (at least
+// sweep_waves() slots, checked by the caller) and nothing is allocated.
+void run_fused(ofl_grid *g, int iters, float omega, double *static_parts = nullptr) {
     grid_ensure_device(g);
     std::vector<Xfer> xs;
     const bool fuse_r = (g->fusion & OFL_FUSE_RESIDUAL) != 0;
     const bool swap = (g->fusion & OFL_FUSE_COPYBACK_SWAP) != 0;
-    if (fuse_r) {
+    double *parts = static_parts;
+    if (fuse_r && !static_parts) {
         const long long need = sweep_waves(g->I, g->J, g->K, g->tile);
         if (need > g->fused_parts_cap) {
             grid_sync(g);
@@ -485,6 +489,7 @@ void run_fused(ofl_grid *g, int iters, float omega) {
             g->fused_parts = static_cast<double *>(ptr);
             g->fused_parts_cap = need;
         }
+        parts = g->fused_parts;
     }
     for (int it = 0; it < iters; ++it) {
         xs.clear();
@@ -493,14 +498,14 @@ void run_fused(ofl_grid *g, int iters, float omega) {
         if (swap)
             grid_sync_wrk2_boundary(g);
         prof_begin(g, kS);
-        launch_sweep(g->view, g->tile, g->fmt != OFL_COEF_F32, omega, g->stream, fuse_r ? g->fused_parts : nullptr);
+        launch_sweep(g->view, g->tile, g->fmt != OFL_COEF_F32, omega, g->stream, fuse_r ? parts : nullptr);
         prof_end(g);
         g->stats.gpu_nests[kS] += 1;
         xs.clear();
         plan_after(it, kS, true, OFL_XFER_HOISTED, g->valid, xs);
         if (fuse_r) {
             prof_begin(g, kR);
-            launch_finalize(g->fused_parts, sweep_waves(g->I, g->J, g->K, g->tile), omega, g->view.gosa, g->stream,
+            launch_finalize(parts, sweep_waves(g->I, g->J, g->K, g->tile), omega, g->view.gosa, g->stream,
                             g->view.partials, kResidualBlocks);
             prof_end(g);
         } else {
@@ -1062,6 +1067,40 @@ int ofl_jacobi_run(ofl_grid *g, int iters, float omega, double *gosa_out) {
             plan_sync_host(iters, g->valid, xs);
             grid_exec(g, xs);
         }
+        const double gosa = grid_fetch_gosa(g);
+        if (gosa_out)
+            *gosa_out = gosa;
+    });
+}
+
+int ofl_jacobi_run_static(ofl_grid *g, int iters, float omega, double *gosa_out) {
+    return grid_call(g, [&] {
+        if (iters < 0)
+            fail(OFL_EINVAL, "iters must be >= 0");
+        if (!std::isfinite(omega) || omega == 0.f)
+            fail(OFL_EINVAL, "omega must be finite and non-zero");
+        if (!g->dev_ready || !g->in_region)
+            fail(OFL_ESTATE, "ofl_jacobi_run_static needs the grid resident: open a data region (ofl_data_enter) first");
+        if (g->mask != OFL_MASK_ALL_GPU || g->mode != OFL_XFER_HOISTED || !grid_whole_nests(g))
+            fail(OFL_ENOTSUP, "ofl_jacobi_run_static runs gene 111 with hoisted transfers and whole nests only");
+        if (g->batch_refs > 0)
+            fail(OFL_ESTATE, "the grid belongs to a batch");
+        if ((g->fusion & OFL_FUSE_RESIDUAL) == 0)
+            fail(OFL_ENOTSUP, "ofl_jacobi_run_static runs the fused residual: set OFL_FUSE_RESIDUAL (ofl_set_fusion)");
+        if (g->profiling)
+            fail(OFL_ENOTSUP, "profiling creates HIP events; switch it off for ofl_jacobi_run_static");
+        const long long need = sweep_waves(g->I, g->J, g->K, g->tile);
+        if (need > kStaticScratchParts)
+            fail(OFL_EINVAL, "the grid's sweep needs " + std::to_string(need) +
+                                 " residual partials, more than the static scratch holds (" +
+                                 std::to_string(kStaticScratchParts) + "); use a tile with longer k-chunks, or ofl_jacobi_run");
+        if (iters == 0) {
+            if (gosa_out)
+                *gosa_out = std::numeric_limits<double>::quiet_NaN();
+            return;
+        }
+        grid_ensure_device(g);  // device state exists: selects the grid's device only
+        run_fused(g, iters, omega, static_scratch(g->device));
         const double gosa = grid_fetch_gosa(g);
         if (gosa_out)
             *gosa_out = gosa;

@@ -27,8 +27,10 @@
 
 #include <algorithm>
 #include <array>
+#include <mutex>
 #include <type_traits>
 #include <utility>
+#include <vector>
 
 #include "ofl_internal.hpp"
 
@@ -1120,6 +1122,32 @@ void launch_stream(const float *const *src32, int n32, const uint16_t *const *sr
     else
         fail(OFL_ENOTSUP, "stream probe patterns: 13 FP32 sources, or 1 FP32 and 12 bfloat16 sources");
     check_launch("stream kernel launch");
+}
+
+// The fused sweep's per-wave residual partials of ofl_jacobi_run_static live
+// here instead of in memory the library allocates. Every slot a launch reads is
+// written by the same launch's sweep first, so nothing needs clearing between
+// calls. In host code the name stands for a host-side shadow, not a device
+// address: only the address hipGetSymbolAddress returns for the current device
+// may reach a kernel.
+static __device__ __align__(256) double scratch[kStaticScratchParts];
+
+double *static_scratch(int device) {
+    static std::mutex mu;
+    static std::vector<double *> ptrs;
+    std::lock_guard<std::mutex> lock(mu);
+    if (device < 0)
+        fail(OFL_EINVAL, "static scratch: negative device ordinal");
+    if (static_cast<size_t>(device) >= ptrs.size())
+        ptrs.resize(static_cast<size_t>(device) + 1, nullptr);
+    if (!ptrs[device]) {
+        void *ptr = nullptr;
+        hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(static scratch)");
+        if (!ptr)
+            fail(OFL_EDEVICE, "hipGetSymbolAddress returned no address for the static scratch");
+        ptrs[device] = static_cast<double *>(ptr);
+    }
+    return ptrs[device];
 }
 
 int device_cu_count(int device) {

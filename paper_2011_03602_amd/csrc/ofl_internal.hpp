@@ -157,4 +157,12 @@ void launch_gemm_f32(int M, int N, int K, const float *A, int lda, const float *
 
 int device_cu_count(int device);
 
+// Library-owned device scratch for the entry point that allocates nothing
+// (ofl_jacobi_run_static): kStaticScratchParts FP64 slots per device, held
+// until the process ends. static_scratch() resolves this device's address of
+// the array (the current device must be `device`); every call on a device
+// shares the same slots.
+constexpr long long kStaticScratchParts = 1LL << 19;  // 4 MiB
+double *static_scratch(int device);
+
 }  // namespace ofl

@@ -23,6 +23,7 @@
 void stand_in_fail_call(long n);
 long stand_in_calls(void);
 long stand_in_live(void);
+long stand_in_alloc_calls(void);
 
 #define CHECK(c)                                                                                       \
     do {                                                                                               \
@@ -111,6 +112,7 @@ static int grid_refuses(ofl_grid *g) {
     ofl_tile t = {4, 4, 2, 1, 0};
     CHECK(ofl_jacobi_run(g, 1, 0.8f, &x) == OFL_EDEVICE);
     CHECK(ofl_residual(g, &x) == OFL_EDEVICE);
+    CHECK(ofl_jacobi_run_static(g, 1, 0.8f, &x) == OFL_EDEVICE);
     CHECK(ofl_set_offload_mask(g, 0u, OFL_XFER_HOISTED) == OFL_EDEVICE);
     CHECK(ofl_set_regions(g, 7u, lev, OFL_XFER_HOISTED) == OFL_EDEVICE);
     CHECK(ofl_set_loop_gene(g, 1u, OFL_XFER_HOISTED) == OFL_EDEVICE);
@@ -265,9 +267,61 @@ static int batch_case(long n, long *calls, int *failed) {
     return 0;
 }
 
+/* ofl_jacobi_run_static: its preconditions are refused before any work, and
+ * on a resident fused grid it makes no HIP call that allocates or releases
+ * (memory, streams, events, graphs), where ofl_jacobi_run takes its partials. */
+static int static_case(void) {
+    problem pb;
+    make(&pb, 37, 9, 7);
+    const long live0 = stand_in_live();
+    ofl_grid_desc d = desc_of(&pb, OFL_COEF_F32);
+    ofl_grid *g = NULL;
+    CHECK(ofl_grid_create(&d, &g) == OFL_OK);
+    double x = 0.0;
+    CHECK(ofl_jacobi_run_static(g, 2, 0.8f, &x) == OFL_ESTATE); /* no device state */
+    CHECK(ofl_jacobi_run_static(g, -1, 0.8f, &x) == OFL_EINVAL);
+    CHECK(ofl_jacobi_run_static(g, 2, 0.0f, &x) == OFL_EINVAL);
+    CHECK(ofl_set_fusion(g, OFL_FUSE_RESIDUAL) == OFL_OK);
+    CHECK(ofl_jacobi_run_static(g, 2, 0.8f, &x) == OFL_ESTATE); /* device state, no data region */
+    CHECK(ofl_data_enter(g) == OFL_OK);
+    long a0 = stand_in_alloc_calls();
+    CHECK(ofl_jacobi_run_static(g, 3, 0.8f, &x) == OFL_OK);
+    CHECK(ofl_set_fusion(g, OFL_FUSE_RESIDUAL | OFL_FUSE_COPYBACK_SWAP) == OFL_OK);
+    CHECK(ofl_jacobi_run_static(g, 3, 0.8f, &x) == OFL_OK);
+    CHECK(ofl_jacobi_run_static(g, 0, 0.8f, &x) == OFL_OK && isnan(x));
+    CHECK(stand_in_alloc_calls() == a0);
+    CHECK(ofl_jacobi_run(g, 1, 0.8f, &x) == OFL_OK); /* the allocating form takes its partials */
+    CHECK(stand_in_alloc_calls() > a0);
+    a0 = stand_in_alloc_calls();
+    CHECK(ofl_jacobi_run_static(g, 2, 0.8f, &x) == OFL_OK);
+    CHECK(stand_in_alloc_calls() == a0);
+    CHECK(ofl_set_fusion(g, OFL_FUSE_COPYBACK_SWAP) == OFL_OK);
+    CHECK(ofl_jacobi_run_static(g, 1, 0.8f, &x) == OFL_ENOTSUP); /* no fused residual */
+    CHECK(ofl_set_fusion(g, OFL_FUSE_RESIDUAL) == OFL_OK);
+    CHECK(ofl_set_profiling(g, 1) == OFL_OK);
+    CHECK(ofl_jacobi_run_static(g, 1, 0.8f, &x) == OFL_ENOTSUP); /* events would be created */
+    CHECK(ofl_set_profiling(g, 0) == OFL_OK);
+    CHECK(ofl_set_offload_mask(g, 5u, OFL_XFER_HOISTED) == OFL_OK);
+    CHECK(ofl_jacobi_run_static(g, 1, 0.8f, &x) == OFL_ENOTSUP); /* not gene 111 */
+    CHECK(ofl_set_offload_mask(g, OFL_MASK_ALL_GPU, OFL_XFER_PER_ITER) == OFL_OK);
+    CHECK(ofl_jacobi_run_static(g, 1, 0.8f, &x) == OFL_ENOTSUP); /* per-iteration placement */
+    CHECK(ofl_set_offload_mask(g, OFL_MASK_ALL_GPU, OFL_XFER_HOISTED) == OFL_OK);
+    CHECK(ofl_jacobi_run_static(g, 1, 0.8f, &x) == OFL_OK);
+    CHECK(ofl_data_exit(g) == OFL_OK);
+    CHECK(ofl_jacobi_run_static(g, 1, 0.8f, &x) == OFL_ESTATE); /* region closed */
+    ofl_grid_destroy(g);
+    CHECK(stand_in_live() == live0);
+    drop(&pb);
+    return 0;
+}
+
 int main(void) {
     long calls = 0, total = 0;
     int failed = 0, sticky = 0;
+
+    /* the entry point that allocates nothing */
+    CHECK(static_case() == 0);
+    printf("static-scratch run: no allocating HIP call\n");
 
     /* grids whose device state exists */
     CHECK(grid_case(0, &total, &failed) == 0 && !failed && total > 40);

@@ -21,6 +21,7 @@ namespace {
 long g_calls = 0;    // HIP calls since the last stand_in_fail_call
 long g_fail_at = 0;  // the call that fails (1-based); 0: none
 long g_live = 0;     // allocations and tokens not yet released
+long g_alloc_calls = 0;  // calls that allocate or release device memory, streams, events or graphs
 bool g_capturing = false;
 
 bool next_fails() {
@@ -36,11 +37,13 @@ bool next_fails() {
 template <class T>
 T token() {
     ++g_live;
+    ++g_alloc_calls;
     return reinterpret_cast<T>(new char[16]);
 }
 
 template <class T>
 void release(T t) {
+    ++g_alloc_calls;
     if (t) {
         --g_live;
         delete[] reinterpret_cast<char *>(t);
@@ -63,6 +66,8 @@ extern "C" void stand_in_fail_call(long n) {
 extern "C" long stand_in_calls(void) { return g_calls; }
 
 extern "C" long stand_in_live(void) { return g_live; }
+
+extern "C" long stand_in_alloc_calls(void) { return g_alloc_calls; }
 
 hipError_t hipGetDeviceCount(int *count) {
     STAND_IN_STEP();
@@ -93,11 +98,13 @@ hipError_t hipMalloc(void **ptr, size_t size) {
         return hipErrorOutOfMemory;
     std::memset(p, 0, bytes == 0 ? 256 : bytes);
     ++g_live;
+    ++g_alloc_calls;
     *ptr = p;
     return hipSuccess;
 }
 
 hipError_t hipFree(void *ptr) {
+    ++g_alloc_calls;
     if (ptr) {
         --g_live;
         std::free(ptr);

@@ -35,5 +35,6 @@ void launch_gemm_f32(int, int, int, const float *, int, const float *, int, floa
     no_device();
 }
 int device_cu_count(int) { no_device(); }
+double *static_scratch(int) { no_device(); }
 
 }  // namespace ofl

@@ -339,3 +339,19 @@ def test_gemm_argument_checks_need_no_gpu():
         assert e.value.code == ofl.OFL_EINVAL, args
     ofl.ofl_gemm_f32(0, 4, 3, 0, 3, 0, 4, 0, 4, None)  # empty result: nothing read or written
     ofl.ofl_gemm_f32(5, 0, 3, 0, 3, 0, 0, 0, 0, None)
+
+
+def test_static_run_refuses_a_grid_that_is_not_resident():
+    """ofl_jacobi_run_static allocates nothing, so it needs the device state and
+    an open data region; here neither exists and nothing runs."""
+    g = ofl.Grid(synth.make_problem(6, 5, 4))
+    p0 = g.p.copy()
+    with pytest.raises(ofl.OflError) as e:
+        ofl.ofl_jacobi_run_static(g.handle, 2, OMEGA)
+    assert e.value.code == ofl.OFL_ESTATE and "data region" in ofl.ofl_last_error()
+    for bad in ((-1, OMEGA), (1, 0.0), (1, float("inf"))):
+        with pytest.raises(ofl.OflError) as e:
+            ofl.ofl_jacobi_run_static(g.handle, *bad)
+        assert e.value.code == ofl.OFL_EINVAL
+    assert np.array_equal(g.p, p0)
+    g.close()
