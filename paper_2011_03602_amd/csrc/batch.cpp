@@ -73,6 +73,7 @@ void batch_upload_views(ofl_batch *b) {
         views[g] = b->grids[g]->view;
         views[g].partials = static_cast<double *>(b->d_partials) + b->partial_base[g];
         views[g].nseg = b->nseg.empty() ? 0 : b->nseg[g];
+        views[g].vec = b->gvec.empty() ? 0 : b->gvec[g];
         swapped[g] = views[g];
         std::swap(swapped[g].p, swapped[g].wrk2);
     }
@@ -176,22 +177,25 @@ void batch_build_tables(ofl_batch *b) {
     };
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return interior(x) > interior(y); });
 
-    // Items are grouped by the vector width their grid runs with (one batched
-    // launch per width); with tile.vec == 0 each grid gets the width that
-    // leaves the fewest idle lanes on its interior rows.
-    std::vector<SweepItem> sitems_by[3];
-    std::vector<RowItem> ritems_by[3];
+    // One item list per nest for every grid, largest grid first. With
+    // tile.vec == 0 each grid gets the width that leaves the fewest idle lanes
+    // on its interior rows, recorded in its view: one launch then runs items
+    // of every width, each at its grid's own (no launch per width, so the
+    // small grids fill the tail of the large ones instead of running after it).
+    std::vector<SweepItem> sitems;
+    std::vector<RowItem> ritems;
     std::vector<int> range(static_cast<size_t>(n) + 1, 0);
     std::vector<int> count(static_cast<size_t>(n), 0);
     const int rows_per_item = kRowsPerWaveItem * (kResidualThreads / kWave);
     b->nseg.assign(static_cast<size_t>(n), 0);
+    b->gvec.assign(static_cast<size_t>(n), 0);
     for (int g : order) {
         const ofl_grid *q = b->grids[static_cast<size_t>(g)];
         TileCfg t = b->tile;
         int pvec = 0, nseg = 0;
         const bool packed = batch_packed(q->I, q->J, q->lay.pitch, b->tile, &pvec, &nseg);
         t.vec = packed ? pvec : (b->tile.vec > 0 ? b->tile.vec : batch_auto_vec(q->I));
-        const int c = t.vec == 1 ? 0 : (t.vec == 2 ? 1 : 2);
+        b->gvec[static_cast<size_t>(g)] = t.vec;
         int nti, nfb, nmc;
         if (packed) {
             // one "line" per segment; the kernels find the segment from fblock
@@ -202,13 +206,13 @@ void batch_build_tables(ofl_batch *b) {
         } else {
             sweep_shape(q->I, q->J, q->K, t, &nti, &nfb, &nmc);
         }
-        const size_t first_item = sitems_by[c].size();
+        const size_t first_item = sitems.size();
         for (int mc = 0; mc < nmc; ++mc)
             for (int fb = 0; fb < nfb; ++fb)
                 for (int it = 0; it < nti; ++it)
-                    sitems_by[c].push_back({g, it, fb, mc});
+                    sitems.push_back({g, it, fb, mc});
         if (!(b->tile.flags & OFL_TILE_XCD_REMAP))
-            xcd_bands(sitems_by[c], first_item, nti * nfb);
+            xcd_bands(sitems, first_item, nti * nfb);
         const long long nrt_l = packed ? static_cast<long long>(nseg) * (q->K - 2)
                                        : static_cast<long long>(nti) * (q->J - 2) * (q->K - 2);
         if (nrt_l > 0x7fffffffLL)
@@ -216,21 +220,15 @@ void batch_build_tables(ofl_batch *b) {
         const int nrt = static_cast<int>(nrt_l);
         int slot = 0;
         for (int first = 0; first < nrt; first += rows_per_item) {
-            ritems_by[c].push_back({g, first, std::min(rows_per_item, nrt - first), slot});
+            ritems.push_back({g, first, std::min(rows_per_item, nrt - first), slot});
             ++slot;
         }
         count[static_cast<size_t>(g)] = slot;
     }
-    std::vector<SweepItem> sitems;
-    std::vector<RowItem> ritems;
-    for (int c = 0; c < 3; ++c) {
-        b->s_off[c] = static_cast<int>(sitems.size());
-        b->s_cnt[c] = static_cast<int>(sitems_by[c].size());
-        b->r_off[c] = static_cast<int>(ritems.size());
-        b->r_cnt[c] = static_cast<int>(ritems_by[c].size());
-        sitems.insert(sitems.end(), sitems_by[c].begin(), sitems_by[c].end());
-        ritems.insert(ritems.end(), ritems_by[c].begin(), ritems_by[c].end());
-    }
+    if (sitems.size() > 0x7fffffffULL / static_cast<size_t>(std::max(1, b->tile.rows)) || ritems.size() > 0x7fffffffULL)
+        fail(OFL_EINVAL, "the batch has too many work items");
+    b->s_cnt = static_cast<int>(sitems.size());
+    b->r_cnt = static_cast<int>(ritems.size());
     for (int g = 0; g < n; ++g)
         range[static_cast<size_t>(g) + 1] = range[static_cast<size_t>(g)] + count[static_cast<size_t>(g)];
     const hipStream_t s = b->stream;
@@ -297,32 +295,24 @@ void batch_enqueue(ofl_batch *b, int iters, float omega) {
     const bool fuse_r = (b->fusion & OFL_FUSE_RESIDUAL) != 0;
     const bool swap = (b->fusion & OFL_FUSE_COPYBACK_SWAP) != 0;
     const int n = static_cast<int>(b->grids.size());
-    const int vecs[3] = {1, 2, 4};
+    // tile.vec 0: every item runs at its grid's own width (views[].vec)
+    const int vec = b->tile.vec;
     for (int it = 0; it < iters; ++it) {
         const GridView *views = (swap && (it & 1)) ? views_odd : views_even;
-        for (int c = 0; c < 3; ++c) {
-            if (b->s_cnt[c] == 0)
-                continue;
-            TileCfg t = b->tile;
-            t.vec = vecs[c];
-            launch_batch_sweep(views, sitems + b->s_off[c], b->s_cnt[c], t, b->fmt != OFL_COEF_F32, omega,
-                               blocks_for(b, b->s_cnt[c]), b->stream,
-                               fuse_r ? fparts + static_cast<long long>(b->s_off[c]) * b->tile.rows : nullptr);
-        }
+        if (b->s_cnt > 0)
+            launch_batch_sweep(views, sitems, b->s_cnt, b->tile, b->fmt != OFL_COEF_F32, omega,
+                               blocks_for(b, b->s_cnt), b->stream, fuse_r ? fparts : nullptr);
         if (fuse_r) {
             launch_batch_finalize_parts(views, fparts, frange, n, omega, b->stream);
         } else {
-            for (int c = 0; c < 3; ++c)
-                if (b->r_cnt[c] > 0)
-                    launch_batch_residual(views, ritems + b->r_off[c], b->r_cnt[c], vecs[c], b->sum_mode,
-                                          b->tile.flags, blocks_for(b, b->r_cnt[c]), b->stream);
+            if (b->r_cnt > 0)
+                launch_batch_residual(views, ritems, b->r_cnt, vec, b->sum_mode, b->tile.flags,
+                                      blocks_for(b, b->r_cnt), b->stream);
             launch_batch_finalize(views, range, n, omega, b->stream);
         }
-        if (!swap)
-            for (int c = 0; c < 3; ++c)
-                if (b->r_cnt[c] > 0)
-                    launch_batch_copyback(views, ritems + b->r_off[c], b->r_cnt[c], vecs[c], b->tile.flags,
-                                          blocks_for(b, b->r_cnt[c]), b->stream, true);
+        if (!swap && b->r_cnt > 0)
+            launch_batch_copyback(views, ritems, b->r_cnt, vec, b->tile.flags, blocks_for(b, b->r_cnt), b->stream,
+                                  true);
     }
 }
 
@@ -438,6 +428,8 @@ int ofl_batch_create(ofl_grid *const *grids, int n, const ofl_tile *tile, ofl_ba
         std::string why;
         if (tile && !(tile_valid(*tile, &why) || batch_auto_vec_tile(*tile)))
             fail(OFL_EINVAL, why);
+        if (tile && tile->vec == 8)
+            fail(OFL_ENOTSUP, "batched sweeps run 1, 2 or 4 points per lane (tile.vec 8 is for single grids)");
         for (int t = 0; t < n; ++t) {
             if (!grids[t])
                 fail(OFL_EINVAL, "a grid handle is NULL");
@@ -507,6 +499,8 @@ int ofl_batch_set_tile(ofl_batch *b, const ofl_tile *tile) {
         std::string why;
         if (!tile_valid(*tile, &why) && !batch_auto_vec_tile(*tile))
             fail(OFL_EINVAL, why);
+        if (tile->vec == 8)
+            fail(OFL_ENOTSUP, "batched sweeps run 1, 2 or 4 points per lane (tile.vec 8 is for single grids)");
         const TileCfg c = to_cfg(*tile);
         if (c.vec != b->tile.vec || c.rows != b->tile.rows || c.kchunk != b->tile.kchunk ||
             c.flags != b->tile.flags || c.occupancy != b->tile.occupancy) {

@@ -26,8 +26,10 @@ struct ofl_batch {
     void *d_ritems = nullptr;
     void *d_range = nullptr;
     void *d_partials = nullptr;
-    int s_off[3] = {}, s_cnt[3] = {};  // sweep items per vector-width class (1, 2, 4)
-    int r_off[3] = {}, r_cnt[3] = {};  // residual/copy-back items per class
+    int s_cnt = 0;  // sweep items (every grid's, largest grid first)
+    int r_cnt = 0;  // residual/copy-back items
+
+    std::vector<int> gvec;          // per grid, its points per lane in the batch
 
     std::vector<int> partial_base;  // per grid, its first residual partial
     std::vector<int> nseg;          // per grid, segments per plane in packed rows (0: one row per wave)

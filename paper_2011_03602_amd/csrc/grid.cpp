@@ -84,8 +84,10 @@ bool tile_valid(const ofl_tile &t, std::string *why) {
             *why = m;
         return false;
     };
-    if (t.vec != 1 && t.vec != 2 && t.vec != 4)
-        return bad("tile.vec must be 1, 2 or 4");
+    if (t.vec != 1 && t.vec != 2 && t.vec != 4 && t.vec != 8)
+        return bad("tile.vec must be 1, 2, 4 or 8");
+    if (t.vec == 8 && (t.flags & OFL_TILE_MARCH_J))
+        return bad("tile.vec 8 (two rows per wave) marches along k only: no OFL_TILE_MARCH_J");
     if (t.rows < 1 || t.rows > 8)
         return bad("tile.rows must be in 1..8");
     if (t.kchunk < 1 || t.kchunk > 1024)
@@ -140,7 +142,9 @@ TileCfg default_tile(int I, int fmt, unsigned fusion) {
 void sweep_shape(int I, int J, int K, const TileCfg &t, int *nti, int *nfb, int *nmc) {
     const bool march_j = (t.flags & OFL_TILE_MARCH_J) != 0;
     *nti = itiles(I, t.vec);
-    *nfb = ((march_j ? K : J) - 2 + t.rows - 1) / t.rows;
+    // lines per work-group: one per wave, or two rows per wave at 8 points per lane
+    const int lines = t.rows * (t.vec == 8 ? 2 : 1);
+    *nfb = ((march_j ? K : J) - 2 + lines - 1) / lines;
     *nmc = ((march_j ? J : K) - 2 + t.kchunk - 1) / t.kchunk;
 }
 
@@ -217,6 +221,7 @@ void grid_ensure_device(ofl_grid *g) {
     v.K = g->K;
     v.pitch = g->lay.pitch;
     v.nseg = 0;
+    v.vec = 0;
     v.plane = static_cast<long long>(g->lay.plane);
     v.partials = reinterpret_cast<double *>(g->block + g->lay.partials_off);
     v.gosa = reinterpret_cast<double *>(g->block + g->lay.gosa_off);
@@ -1182,6 +1187,8 @@ int ofl_set_tile(ofl_grid *g, const ofl_tile *tile) {
             fail(OFL_EINVAL, "tile is NULL");
         if (!tile_valid(*tile, &why))
             fail(OFL_EINVAL, why);
+        if (tile->vec == 8 && make_layout(g->I, g->J, g->K, g->fmt, g->row_align).pitch % 8 != 0)
+            fail(OFL_EINVAL, "tile.vec 8 needs a row pitch that is a multiple of 8 elements (row_align 0, 8, 16 or 32)");
         g->tile = to_cfg(*tile);
         g->tile_chosen = true;
     });

@@ -100,12 +100,24 @@ __device__ __forceinline__ void load_f32(const float *ptr, float (&v)[VEC]) {
         f2 x = ld<NT>(reinterpret_cast<const f2 *>(ptr));
         v[0] = x.x;
         v[1] = x.y;
-    } else {
+    } else if constexpr (VEC == 4) {
         f4 x = ld<NT>(reinterpret_cast<const f4 *>(ptr));
         v[0] = x.x;
         v[1] = x.y;
         v[2] = x.z;
         v[3] = x.w;
+    } else {
+        static_assert(VEC == 8, "vector width");
+        f4 x = ld<NT>(reinterpret_cast<const f4 *>(ptr));
+        f4 y = ld<NT>(reinterpret_cast<const f4 *>(ptr) + 1);
+        v[0] = x.x;
+        v[1] = x.y;
+        v[2] = x.z;
+        v[3] = x.w;
+        v[4] = y.x;
+        v[5] = y.y;
+        v[6] = y.z;
+        v[7] = y.w;
     }
 }
 
@@ -116,9 +128,15 @@ __device__ __forceinline__ void store_f32(float *ptr, const float (&v)[VEC]) {
     } else if constexpr (VEC == 2) {
         f2 x = {v[0], v[1]};
         st<NT>(reinterpret_cast<f2 *>(ptr), x);
-    } else {
+    } else if constexpr (VEC == 4) {
         f4 x = {v[0], v[1], v[2], v[3]};
         st<NT>(reinterpret_cast<f4 *>(ptr), x);
+    } else {
+        static_assert(VEC == 8, "vector width");
+        f4 x = {v[0], v[1], v[2], v[3]};
+        f4 y = {v[4], v[5], v[6], v[7]};
+        st<NT>(reinterpret_cast<f4 *>(ptr), x);
+        st<NT>(reinterpret_cast<f4 *>(ptr) + 1, y);
     }
 }
 
@@ -136,13 +154,34 @@ __device__ __forceinline__ void load_bf16(const uint16_t *ptr, float bias, float
         unsigned u = ld<NT>(reinterpret_cast<const unsigned *>(ptr));
         v[0] = bias + bf16_lo(u);
         v[1] = bias + bf16_hi(u);
-    } else {
+    } else if constexpr (VEC == 4) {
         u2 x = ld<NT>(reinterpret_cast<const u2 *>(ptr));
         v[0] = bias + bf16_lo(x.x);
         v[1] = bias + bf16_hi(x.x);
         v[2] = bias + bf16_lo(x.y);
         v[3] = bias + bf16_hi(x.y);
+    } else {
+        // 16 bytes per lane: eight bfloat16 values in one load
+        static_assert(VEC == 8, "vector width");
+        u4 x = ld<NT>(reinterpret_cast<const u4 *>(ptr));
+        v[0] = bias + bf16_lo(x.x);
+        v[1] = bias + bf16_hi(x.x);
+        v[2] = bias + bf16_lo(x.y);
+        v[3] = bias + bf16_hi(x.y);
+        v[4] = bias + bf16_lo(x.z);
+        v[5] = bias + bf16_hi(x.z);
+        v[6] = bias + bf16_lo(x.w);
+        v[7] = bias + bf16_hi(x.w);
     }
+}
+
+// Lanes that share one row segment: the whole wave, or, with 8 points per
+// lane, each half of it (a wave then owns two rows of 256 points, so a tile is
+// 256 points wide at every vector width from 4 up and each coefficient load is
+// 16 bytes per lane in the bfloat16 formats).
+template <int VEC>
+constexpr int lanes_per_row() {
+    return VEC == 8 ? kWave / 2 : kWave;
 }
 
 // One row segment of p: this lane's VEC values plus its outer neighbours
@@ -150,24 +189,25 @@ __device__ __forceinline__ void load_bf16(const uint16_t *ptr, float bias, float
 // rows of a step before any neighbour exchange, so that one wait covers the
 // whole step: issue_prow() starts the vector load and the halo load,
 // finish_prow() takes the inner neighbours from the adjacent lanes and the
-// two wave-edge neighbours from the halo value. The halo load is branch-free:
-// lane 63 reads the element after the tile (hr), every other lane the element
+// two segment-edge neighbours from the halo value. `sub` is the lane's index
+// within its row segment. The halo load is branch-free: the segment's last
+// lane reads the element after the tile (hr), every other lane the element
 // before it (hl, one shared cache line). For the first tile of a row that
 // element is row padding or the array's front guard; it only feeds i = 0,
 // which is never stored.
 template <int VEC>
-__device__ __forceinline__ void issue_prow(const float *row, int il, int hl, int hr, int lane, float (&v)[VEC],
+__device__ __forceinline__ void issue_prow(const float *row, int il, int hl, int hr, int sub, float (&v)[VEC],
                                            float &h) {
     load_f32<VEC, false>(row + il, v);
-    h = row[lane == kWave - 1 ? hr : hl];
+    h = row[sub == lanes_per_row<VEC>() - 1 ? hr : hl];
 }
 
 template <int VEC>
-__device__ __forceinline__ void finish_prow(const float (&v)[VEC], float h, int lane, float &l, float &r) {
+__device__ __forceinline__ void finish_prow(const float (&v)[VEC], float h, int sub, float &l, float &r) {
     const float up = __shfl_up(v[VEC - 1], 1, kWave);
     const float dn = __shfl_down(v[0], 1, kWave);
-    l = (lane == 0) ? h : up;
-    r = (lane == kWave - 1) ? h : dn;
+    l = (sub == 0) ? h : up;
+    r = (sub == lanes_per_row<VEC>() - 1) ? h : dn;
 }
 
 template <int VEC, bool BF16, bool NT>
@@ -194,6 +234,9 @@ __device__ __forceinline__ void load_coefs(const GridView &g, long long off, flo
 // j = m0..m1-1 (consecutive steps one row apart, so every stream the wave reads
 // advances through contiguous memory). Either way rows j-1..j+1 of planes
 // k-1..k+1 stay in registers and each step loads only the three new rows.
+// With 8 points per lane (k-march, unpacked rows only) the wave owns rows
+// `fixed` and `fixed`+1, one per half-wave; a half whose row lies past J-2
+// loads row J-2 and stores nothing.
 template <int VEC, bool BF16, int FLAGS>
 __device__ __forceinline__ void sweep_march(const GridView &g, int ts, int fixed, int m0, int m1, float omega,
                                             double *part) {
@@ -202,20 +245,26 @@ __device__ __forceinline__ void sweep_march(const GridView &g, int ts, int fixed
     constexpr bool kNtStores = (FLAGS & OFL_TILE_NT_STORES) != 0;
     constexpr bool kPrefetch = (FLAGS & OFL_TILE_PREFETCH) != 0;
     constexpr bool kMarchJ = (FLAGS & OFL_TILE_MARCH_J) != 0;
+    constexpr int kLpr = lanes_per_row<VEC>();
+    static_assert(VEC != 8 || !kMarchJ, "8 points per lane march along k only");
     const int lane = threadIdx.x & (kWave - 1);
-    const int ib = ts + lane * VEC;
-    const bool packed = !kMarchJ && g.nseg > 0;
+    const int sub = lane & (kLpr - 1);
+    const int ib = ts + sub * VEC;
+    const bool packed = !kMarchJ && VEC != 8 && g.nseg > 0;
     const int flat_end = (g.J - 1) * g.pitch;  // packed: first point after row J-2
     // Lanes whose vector starts past the row's last element (packed: past row
     // J-2) load the last vector before that instead (same cache line, no extra
     // HBM traffic); their results are never stored.
     const int il = packed ? min(ib, flat_end - VEC) : min(ib, ((g.I - 1) / VEC) * VEC);
     const int hl = ts - 1;
-    const int hr = packed ? min(ts + kWave * VEC, flat_end - 1) : ts + kWave * VEC;
+    const int hr = packed ? min(ts + kLpr * VEC, flat_end - 1) : ts + kLpr * VEC;
     // i of the lane's first point, and whether its row is an interior one
     const int jr = packed ? ib / g.pitch : 0;
     const int i0 = ib - jr * g.pitch;
-    const bool row_ok = !packed || (jr >= 1 && jr <= g.J - 2);
+    const int jown = VEC == 8 ? fixed + lane / kLpr : fixed;  // this lane's row (k-march)
+    const bool row_ok = packed ? (jr >= 1 && jr <= g.J - 2) : (VEC != 8 || jown <= g.J - 2);
+    if constexpr (VEC == 8)
+        fixed = min(jown, g.J - 2);
     const long long pitch = g.pitch;
     const long long plane = g.plane;
     const float *__restrict__ p = g.p;
@@ -236,18 +285,18 @@ __device__ __forceinline__ void sweep_march(const GridView &g, int ts, int fixed
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
                 if constexpr (kMarchJ)
-                    issue_prow<VEC>(row(m0 - 1 + a, fixed - 1 + b), il, hl, hr, lane, P[a][b], h[a][b]);
+                    issue_prow<VEC>(row(m0 - 1 + a, fixed - 1 + b), il, hl, hr, sub, P[a][b], h[a][b]);
                 else
-                    issue_prow<VEC>(row(fixed - 1 + b, m0 - 1 + a), il, hl, hr, lane, P[b][a], h[a][b]);
+                    issue_prow<VEC>(row(fixed - 1 + b, m0 - 1 + a), il, hl, hr, sub, P[b][a], h[a][b]);
             }
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
                 if constexpr (kMarchJ)
-                    finish_prow<VEC>(P[a][b], h[a][b], lane, EL[a][b], ER[a][b]);
+                    finish_prow<VEC>(P[a][b], h[a][b], sub, EL[a][b], ER[a][b]);
                 else
-                    finish_prow<VEC>(P[b][a], h[a][b], lane, EL[b][a], ER[b][a]);
+                    finish_prow<VEC>(P[b][a], h[a][b], sub, EL[b][a], ER[b][a]);
             }
     }
 
@@ -274,9 +323,9 @@ __device__ __forceinline__ void sweep_march(const GridView &g, int ts, int fixed
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
             if constexpr (kMarchJ)
-                issue_prow<VEC>(row(j + 1, k - 1 + b), il, hl, hr, lane, P[2][b], h[b]);
+                issue_prow<VEC>(row(j + 1, k - 1 + b), il, hl, hr, sub, P[2][b], h[b]);
             else
-                issue_prow<VEC>(row(j - 1 + b, k + 1), il, hl, hr, lane, P[b][2], h[b]);
+                issue_prow<VEC>(row(j - 1 + b, k + 1), il, hl, hr, sub, P[b][2], h[b]);
         }
         // Keep every load of the step ahead of the first use, so one wait
         // covers them all instead of the scheduler trading them for registers.
@@ -284,9 +333,9 @@ __device__ __forceinline__ void sweep_march(const GridView &g, int ts, int fixed
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
             if constexpr (kMarchJ)
-                finish_prow<VEC>(P[2][b], h[b], lane, EL[2][b], ER[2][b]);
+                finish_prow<VEC>(P[2][b], h[b], sub, EL[2][b], ER[2][b]);
             else
-                finish_prow<VEC>(P[b][2], h[b], lane, EL[b][2], ER[b][2]);
+                finish_prow<VEC>(P[b][2], h[b], sub, EL[b][2], ER[b][2]);
         }
 
         float out[VEC];
@@ -295,14 +344,23 @@ __device__ __forceinline__ void sweep_march(const GridView &g, int ts, int fixed
             // neighbour at i+1 / i-1 of element e in row r, plane q
             auto rt = [&](int r, int q) { return e < VEC - 1 ? P[r][q][e + 1] : ER[r][q]; };
             auto lf = [&](int r, int q) { return e > 0 ? P[r][q][e - 1] : EL[r][q]; };
+            // Every product is fused with its sum explicitly, in one fixed
+            // order, so each point gets the same roundings in every tile,
+            // width, batched and fused form (the compiler's own contraction
+            // may pair a different product with each sum per instantiation).
             const float centre = P[1][1][e];
-            float s0 = C[0][e] * rt(1, 1) + C[1][e] * P[2][1][e] + C[2][e] * P[1][2][e];
-            s0 += C[4][e] * ((rt(2, 1) - rt(0, 1)) - (lf(2, 1) - lf(0, 1)));
-            s0 += C[5][e] * ((P[2][2][e] - P[0][2][e]) - (P[2][0][e] - P[0][0][e]));
-            s0 += C[6][e] * ((rt(1, 2) - lf(1, 2)) - (rt(1, 0) - lf(1, 0)));
-            s0 += C[7][e] * lf(1, 1) + C[8][e] * P[0][1][e] + C[9][e] * P[1][0][e] + C[11][e];
-            const float ss = (C[3][e] * s0 - centre) * C[10][e];
-            out[e] = centre + omega * ss;
+            float s0 = C[0][e] * rt(1, 1);
+            s0 = fmaf(C[1][e], P[2][1][e], s0);
+            s0 = fmaf(C[2][e], P[1][2][e], s0);
+            s0 = fmaf(C[4][e], (rt(2, 1) - rt(0, 1)) - (lf(2, 1) - lf(0, 1)), s0);
+            s0 = fmaf(C[5][e], (P[2][2][e] - P[0][2][e]) - (P[2][0][e] - P[0][0][e]), s0);
+            s0 = fmaf(C[6][e], (rt(1, 2) - lf(1, 2)) - (rt(1, 0) - lf(1, 0)), s0);
+            s0 = fmaf(C[7][e], lf(1, 1), s0);
+            s0 = fmaf(C[8][e], P[0][1][e], s0);
+            s0 = fmaf(C[9][e], P[1][0][e], s0);
+            s0 += C[11][e];
+            const float ss = fmaf(C[3][e], s0, -centre) * C[10][e];
+            out[e] = fmaf(omega, ss, centre);
             if constexpr (kFuseR) {
                 // the residual nest's own term, (wrk2 - p) in FP32 squared in FP64
                 if (row_ok && i0 + e >= 1 && i0 + e <= I - 2) {
@@ -390,7 +448,9 @@ __global__ __launch_bounds__(512) void sweep_kernel(GridView g, int chunk, int n
     const int fb = rest % nfb;
     const int mc = rest / nfb;
     const int lines = blockDim.x / kWave;
-    const int fixed = 1 + fb * lines + static_cast<int>(threadIdx.x / kWave);
+    // a wave owns one line, or two rows with 8 points per lane
+    constexpr int kRowsPerWave = kWave / lanes_per_row<VEC>();
+    const int fixed = 1 + (fb * lines + static_cast<int>(threadIdx.x / kWave)) * kRowsPerWave;
     int fixed_last, march_end;
     march_extent<FLAGS>(g, fixed_last, march_end);
     if (fixed > fixed_last) {
@@ -401,11 +461,49 @@ __global__ __launch_bounds__(512) void sweep_kernel(GridView g, int chunk, int n
     }
     const int m0 = 1 + mc * chunk;
     const int m1 = min(m0 + chunk, march_end);
-    sweep_march<VEC, BF16, FLAGS>(g, it * kWave * VEC, fixed, m0, m1, omega, part);
+    sweep_march<VEC, BF16, FLAGS>(g, it * tile_points(VEC), fixed, m0, m1, omega, part);
+}
+
+// One batched sweep item for one wave: its line (or packed segment) and march
+// chunk. part (fused residual) receives the wave's partial, 0 for an idle wave.
+template <int VEC, bool BF16, int FLAGS>
+__device__ __forceinline__ void batch_sweep_item(const GridView &g, const SweepItem &item, int chunk, float omega,
+                                                 int lines, int wave, double *part) {
+    constexpr bool kFuseR = (FLAGS & kFlagFuseResidual) != 0;
+    if constexpr ((FLAGS & OFL_TILE_MARCH_J) == 0) {
+        if (g.nseg > 0) {
+            // packed rows: the work-group's waves own consecutive segments
+            const int seg = item.fblock * lines + wave;
+            if (seg >= g.nseg) {
+                if constexpr (kFuseR)
+                    if ((threadIdx.x & (kWave - 1)) == 0)
+                        *part = 0.0;
+                return;
+            }
+            const int m0 = 1 + item.mchunk * chunk;
+            const int m1 = min(m0 + chunk, g.K - 1);
+            sweep_march<VEC, BF16, FLAGS>(g, packed_seg0(g.pitch) + seg * kWave * VEC, 0, m0, m1, omega, part);
+            return;
+        }
+    }
+    const int fixed = 1 + item.fblock * lines + wave;
+    int fixed_last, march_end;
+    march_extent<FLAGS>(g, fixed_last, march_end);
+    if (fixed > fixed_last) {
+        if constexpr (kFuseR)
+            if ((threadIdx.x & (kWave - 1)) == 0)
+                *part = 0.0;
+        return;
+    }
+    const int m0 = 1 + item.mchunk * chunk;
+    const int m1 = min(m0 + chunk, march_end);
+    sweep_march<VEC, BF16, FLAGS>(g, item.itile * kWave * VEC, fixed, m0, m1, omega, part);
 }
 
 // parts (fused residual only): slot w*lines + wave receives the partial of
-// wave `wave` of item w; every slot of every item is written.
+// wave `wave` of item w; every slot of every item is written. VEC == 0: each
+// item runs at its grid's own width (g.vec: 1, 2 or 4), so one launch covers
+// grids of every width; the branch is uniform over the work-group.
 template <int VEC, bool BF16, int FLAGS>
 __global__ __launch_bounds__(512) void batch_sweep_kernel(const GridView *__restrict__ views,
                                                           const SweepItem *__restrict__ items, int nitems,
@@ -420,34 +518,16 @@ __global__ __launch_bounds__(512) void batch_sweep_kernel(const GridView *__rest
         double *part = nullptr;
         if constexpr (kFuseR)
             part = parts + static_cast<long long>(w) * lines + wave;
-        if constexpr ((FLAGS & OFL_TILE_MARCH_J) == 0) {
-            if (g.nseg > 0) {
-                // packed rows: the work-group's waves own consecutive segments
-                const int seg = item.fblock * lines + wave;
-                if (seg >= g.nseg) {
-                    if constexpr (kFuseR)
-                        if ((threadIdx.x & (kWave - 1)) == 0)
-                            *part = 0.0;
-                    continue;
-                }
-                const int m0 = 1 + item.mchunk * chunk;
-                const int m1 = min(m0 + chunk, g.K - 1);
-                sweep_march<VEC, BF16, FLAGS>(g, packed_seg0(g.pitch) + seg * kWave * VEC, 0, m0, m1, omega, part);
-                continue;
-            }
+        if constexpr (VEC == 0) {
+            if (g.vec == 1)
+                batch_sweep_item<1, BF16, FLAGS>(g, item, chunk, omega, lines, wave, part);
+            else if (g.vec == 2)
+                batch_sweep_item<2, BF16, FLAGS>(g, item, chunk, omega, lines, wave, part);
+            else
+                batch_sweep_item<4, BF16, FLAGS>(g, item, chunk, omega, lines, wave, part);
+        } else {
+            batch_sweep_item<VEC, BF16, FLAGS>(g, item, chunk, omega, lines, wave, part);
         }
-        const int fixed = 1 + item.fblock * lines + wave;
-        int fixed_last, march_end;
-        march_extent<FLAGS>(g, fixed_last, march_end);
-        if (fixed > fixed_last) {
-            if constexpr (kFuseR)
-                if ((threadIdx.x & (kWave - 1)) == 0)
-                    *part = 0.0;
-            continue;
-        }
-        const int m0 = 1 + item.mchunk * chunk;
-        const int m1 = min(m0 + chunk, march_end);
-        sweep_march<VEC, BF16, FLAGS>(g, item.itile * kWave * VEC, fixed, m0, m1, omega, part);
     }
 }
 
@@ -583,7 +663,17 @@ __global__ __launch_bounds__(kResidualThreads) void batch_residual_kernel(const 
         const int first = item.first + wave * per;
         const int count = max(0, min(per, item.first + item.count - first));
         Acc acc = {0.0, 0.f, 0.f};
-        residual_rows<VEC, SUM, NT>(g, first, count, acc);
+        if constexpr (VEC == 0) {
+            // the grid's own width (uniform over the work-group)
+            if (g.vec == 1)
+                residual_rows<1, SUM, NT>(g, first, count, acc);
+            else if (g.vec == 2)
+                residual_rows<2, SUM, NT>(g, first, count, acc);
+            else
+                residual_rows<4, SUM, NT>(g, first, count, acc);
+        } else {
+            residual_rows<VEC, SUM, NT>(g, first, count, acc);
+        }
         const double t = block_sum(acc_value<SUM>(acc));
         if (threadIdx.x == 0)
             views[item.grid].partials[item.partial] = t;
@@ -732,7 +822,16 @@ __global__ __launch_bounds__(kResidualThreads) void batch_copyback_kernel(const 
         const int per = (item.count + kWaves - 1) / kWaves;
         const int first = item.first + wave * per;
         const int count = max(0, min(per, item.first + item.count - first));
-        copyback_rows<VEC, NTL, NTS>(g, first, count, whole_rows != 0);
+        if constexpr (VEC == 0) {
+            if (g.vec == 1)
+                copyback_rows<1, NTL, NTS>(g, first, count, whole_rows != 0);
+            else if (g.vec == 2)
+                copyback_rows<2, NTL, NTS>(g, first, count, whole_rows != 0);
+            else
+                copyback_rows<4, NTL, NTS>(g, first, count, whole_rows != 0);
+        } else {
+            copyback_rows<VEC, NTL, NTS>(g, first, count, whole_rows != 0);
+        }
     }
 }
 
@@ -883,21 +982,43 @@ static_assert((kTemplateFlagMask | kFlagFuseResidual) < kSweepCombos, "sweep lau
 
 int vec_index(int vec) { return vec == 1 ? 0 : (vec == 2 ? 1 : 2); }
 
-SweepLaunch sweep_launcher(int vec, bool bf16, int flags) {
-    static const std::array<SweepLaunch, kSweepCombos> table[2][3] = {
-        {sweep_row<1, false>(SweepFlagSeq{}), sweep_row<2, false>(SweepFlagSeq{}),
-         sweep_row<4, false>(SweepFlagSeq{})},
-        {sweep_row<1, true>(SweepFlagSeq{}), sweep_row<2, true>(SweepFlagSeq{}), sweep_row<4, true>(SweepFlagSeq{})}};
-    return table[bf16 ? 1 : 0][vec_index(vec)][flags & (kSweepCombos - 1)];
+// 8 points per lane: k-march only, so the flag combinations without
+// OFL_TILE_MARCH_J (the host refuses such tiles before any launch).
+template <bool BF16, int F>
+constexpr SweepLaunch sweep_one_vec8() {
+    if constexpr ((F & OFL_TILE_MARCH_J) != 0)
+        return nullptr;
+    else
+        return &sweep_one<8, BF16, F>;
 }
 
+template <bool BF16, int... F>
+constexpr std::array<SweepLaunch, sizeof...(F)> sweep_row_vec8(std::integer_sequence<int, F...>) {
+    return {sweep_one_vec8<BF16, F>()...};
+}
+
+SweepLaunch sweep_launcher(int vec, bool bf16, int flags) {
+    static const std::array<SweepLaunch, kSweepCombos> table[2][4] = {
+        {sweep_row<1, false>(SweepFlagSeq{}), sweep_row<2, false>(SweepFlagSeq{}),
+         sweep_row<4, false>(SweepFlagSeq{}), sweep_row_vec8<false>(SweepFlagSeq{})},
+        {sweep_row<1, true>(SweepFlagSeq{}), sweep_row<2, true>(SweepFlagSeq{}), sweep_row<4, true>(SweepFlagSeq{}),
+         sweep_row_vec8<true>(SweepFlagSeq{})}};
+    const SweepLaunch f = table[bf16 ? 1 : 0][vec == 8 ? 3 : vec_index(vec)][flags & (kSweepCombos - 1)];
+    if (!f)
+        fail(OFL_ENOTSUP, "8 points per lane march along k only (no OFL_TILE_MARCH_J)");
+    return f;
+}
+
+// vec 0: each item at its grid's own width
 BatchSweepLaunch batch_sweep_launcher(int vec, bool bf16, int flags) {
-    static const std::array<BatchSweepLaunch, kSweepCombos> table[2][3] = {
+    if (vec != 0 && vec != 1 && vec != 2 && vec != 4)
+        fail(OFL_ENOTSUP, "batched sweeps run 1, 2 or 4 points per lane");
+    static const std::array<BatchSweepLaunch, kSweepCombos> table[2][4] = {
         {batch_sweep_row<1, false>(SweepFlagSeq{}), batch_sweep_row<2, false>(SweepFlagSeq{}),
-         batch_sweep_row<4, false>(SweepFlagSeq{})},
+         batch_sweep_row<4, false>(SweepFlagSeq{}), batch_sweep_row<0, false>(SweepFlagSeq{})},
         {batch_sweep_row<1, true>(SweepFlagSeq{}), batch_sweep_row<2, true>(SweepFlagSeq{}),
-         batch_sweep_row<4, true>(SweepFlagSeq{})}};
-    return table[bf16 ? 1 : 0][vec_index(vec)][flags & (kSweepCombos - 1)];
+         batch_sweep_row<4, true>(SweepFlagSeq{}), batch_sweep_row<0, true>(SweepFlagSeq{})}};
+    return table[bf16 ? 1 : 0][vec == 0 ? 3 : vec_index(vec)][flags & (kSweepCombos - 1)];
 }
 
 }  // namespace
@@ -973,14 +1094,19 @@ void by_vec_sum_nt(int vec, int sum_mode, bool nt, A &&...a) {
         with_sum(std::integral_constant<int, 1>{});
     else if (vec == 2)
         with_sum(std::integral_constant<int, 2>{});
-    else
+    else if (vec == 4)
         with_sum(std::integral_constant<int, 4>{});
+    else
+        with_sum(std::integral_constant<int, 0>{});  // batches: each item at its grid's width
 }
 
 template <int VEC, int SUM, bool NT>
 struct ResidualLaunch {
     static void run(dim3 grid, dim3 block, hipStream_t s, const GridView &g, int rpw, int nrt) {
-        residual_kernel<VEC, SUM, NT><<<grid, block, 0, s>>>(g, rpw, nrt);
+        if constexpr (VEC == 0)
+            fail(OFL_EINVAL, "a single grid's residual runs 1, 2 or 4 points per lane");
+        else
+            residual_kernel<VEC, SUM, NT><<<grid, block, 0, s>>>(g, rpw, nrt);
     }
 };
 
@@ -996,7 +1122,10 @@ template <int VEC, int NTS, bool NTL>
 struct CopybackLaunch {
     static void run(dim3 grid, dim3 block, hipStream_t s, const GridView &g, int rpw, int nrt, int whole_rows,
                     int fin_n, double omega) {
-        copyback_kernel<VEC, NTL, NTS != 0><<<grid, block, 0, s>>>(g, rpw, nrt, whole_rows, fin_n, omega);
+        if constexpr (VEC == 0)
+            fail(OFL_EINVAL, "a single grid's copy-back runs 1, 2 or 4 points per lane");
+        else
+            copyback_kernel<VEC, NTL, NTS != 0><<<grid, block, 0, s>>>(g, rpw, nrt, whole_rows, fin_n, omega);
     }
 };
 
@@ -1011,6 +1140,7 @@ struct BatchCopybackLaunch {
 }  // namespace
 
 void launch_residual(const GridView &g, int vec, int sum_mode, int flags, float omega, hipStream_t s, bool finalize) {
+    vec = std::min(vec, 4);  // p and wrk2 are FP32: 16 bytes per lane at 4 points
     const int nrt = itiles(g.I, vec) * (g.J - 2) * (g.K - 2);
     const int rpw = rows_per_wave(nrt, kResidualBlocks);
     // Ordinary loads: p and wrk2 then stay in the caches for the copy-back that
@@ -1028,6 +1158,7 @@ void launch_residual(const GridView &g, int vec, int sum_mode, int flags, float 
 
 void launch_copyback(const GridView &g, int vec, int flags, hipStream_t s, bool whole_rows, bool finalize_residual,
                      float omega) {
+    vec = std::min(vec, 4);  // p and wrk2 are FP32: 16 bytes per lane at 4 points
     const int nrt = itiles(g.I, vec) * (g.J - 2) * (g.K - 2);
     const int blocks = grid_for(nrt, (kResidualThreads / kWave) * kRowUnroll * 2, kResidualBlocks * 4);
     const int rpw = rows_per_wave(nrt, blocks);

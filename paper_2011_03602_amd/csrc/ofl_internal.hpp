@@ -70,6 +70,9 @@ struct GridView {
     // segments of 64 * VEC consecutive points per plane (rows 1..J-2), each
     // wave's line running across row ends; 0 for the row-per-wave form.
     int nseg;
+    // Batched grids only: the grid's points per lane (1, 2 or 4) in a launch
+    // whose items mix vector widths; unused elsewhere.
+    int vec;
     long long plane;
     double *partials;  // residual partial sums (batched: base of this grid's range)
     double *gosa;      // device scalar
@@ -93,7 +96,10 @@ bool tile_valid(const ofl_tile &t, std::string *why);
 TileCfg to_cfg(const ofl_tile &t);
 ofl_tile to_tile(const TileCfg &c);
 
-__host__ __device__ inline int itiles(int I, int vec) { return (I - 2) / (kWave * vec) + 1; }
+// Points of one row tile: 64 lanes x vec, except at 8 points per lane, where
+// a wave covers two rows of 32 lanes each (the sweep only).
+__host__ __device__ inline constexpr int tile_points(int vec) { return vec == 8 ? (kWave / 2) * 8 : kWave * vec; }
+__host__ __device__ inline int itiles(int I, int vec) { return (I - 2) / tile_points(vec) + 1; }
 
 // Packed rows (batched grids with short rows): a plane's rows 1..J-2 are cut
 // into segments of 64 * vec consecutive points, the first starting at the

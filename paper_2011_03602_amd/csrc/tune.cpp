@@ -9,7 +9,8 @@
 // generation for a set number of generations; the best gene wins.
 //
 // Gene layout (bit 0 first):
-//   bits 0-1  vec       00:1 01:2 10:4 11: not buildable
+//   bits 0-1  vec       00:1 01:2 10:4 11:8 (single grids, k-march only;
+//                       not buildable for batches or with OFL_TILE_MARCH_J)
 //   bits 2-3  rows      1, 2, 4, 8
 //   bits 4-6  kchunk    1, 2, 4, ..., 128 (the short chunks measure best on
 //                       MI355X: more work-groups keep more loads in flight)
@@ -51,9 +52,9 @@ int gene_bits(bool batch) { return batch ? 15 : 12; }
 
 bool decode(uint32_t gene, bool batch, TileCfg *t) {
     const int v = static_cast<int>(gene & 3u);
-    if (v == 3)
+    if (v == 3 && (batch || ((gene >> 7) & static_cast<uint32_t>(OFL_TILE_MARCH_J))))
         return false;
-    t->vec = v == 0 ? 1 : (v == 1 ? 2 : 4);
+    t->vec = 1 << v;
     t->rows = 1 << ((gene >> 2) & 3u);
     t->kchunk = 1 << ((gene >> 4) & 7u);
     t->flags = static_cast<int>((gene >> 7) & 31u);
@@ -65,7 +66,7 @@ bool decode(uint32_t gene, bool batch, TileCfg *t) {
 }
 
 uint32_t encode(const TileCfg &t, bool batch) {
-    uint32_t g = t.vec == 1 ? 0u : (t.vec == 2 ? 1u : 2u);
+    uint32_t g = t.vec == 1 ? 0u : (t.vec == 2 ? 1u : (t.vec == 4 ? 2u : 3u));
     if (batch && t.vec == 0)
         g |= 1u << 14;
     int r = 0;

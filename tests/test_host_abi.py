@@ -355,3 +355,35 @@ def test_static_run_refuses_a_grid_that_is_not_resident():
         assert e.value.code == ofl.OFL_EINVAL
     assert np.array_equal(g.p, p0)
     g.close()
+
+
+def test_eight_point_tiles_are_checked_against_the_layout():
+    """tile.vec 8 (two rows per wave, 16-byte bfloat16 loads) marches along k
+    only, needs a row pitch that is a multiple of 8 elements, and is refused
+    for batches; the checks run on the host, before any device work."""
+    a = synth.make_problem(45, 9, 7)
+    g = ofl.Grid(a)
+    ofl.ofl_set_tile(g.handle, ofl.tile(vec=8, rows=4, kchunk=2, flags=3))
+    assert ofl.ofl_get_tile(g.handle).vec == 8
+    with pytest.raises(ofl.OflError) as e:
+        ofl.ofl_set_tile(g.handle, ofl.tile(vec=8, rows=4, kchunk=2, flags=ofl.OFL_TILE_MARCH_J))
+    assert e.value.code == ofl.OFL_EINVAL and "MARCH_J" in ofl.ofl_last_error()
+    with pytest.raises(ofl.OflError):
+        ofl.ofl_set_tile(g.handle, ofl.tile(vec=16))
+    g.close()
+    # compact rows: 45 points at a 4-element alignment give a 48-element pitch
+    # (a multiple of 8), 43 points a 44-element one (not)
+    for I, ok in ((45, True), (43, False)):
+        g = ofl.Grid(synth.make_problem(I, 9, 7), row_align=4)
+        if ok:
+            ofl.ofl_set_tile(g.handle, ofl.tile(vec=8, rows=2, kchunk=2))
+        else:
+            with pytest.raises(ofl.OflError) as e:
+                ofl.ofl_set_tile(g.handle, ofl.tile(vec=8, rows=2, kchunk=2))
+            assert e.value.code == ofl.OFL_EINVAL and "pitch" in ofl.ofl_last_error()
+        g.close()
+    g = ofl.Grid(a)
+    with pytest.raises(ofl.OflError) as e:
+        ofl.ofl_batch_create([g.handle], ofl.tile(vec=8, rows=2, kchunk=2))
+    assert e.value.code == ofl.OFL_ENOTSUP
+    g.close()
