@@ -900,6 +900,19 @@ def main():
             out["variants"][name] = run_batch(ofl, probs, fmt, max(1, args.steps // 2), 1, args.tune_batch,
                                               row_align=args.batch_row_align, check=check)
         del probs
+    if not args.skip_variants:
+        # the function-block routine (a matrix product on the matrix cores);
+        # its parity against the FP64 oracle is a GPU test, not part of this line
+        out["variants"]["gemm_f32"] = {"note": "ofl_gemm_f32, FP32 products and accumulation on the matrix cores; "
+                                               "parity: tests/test_gpu_gemm.py against the FP64 oracle_gemm",
+                                       "shapes": []}
+        for M, N, K in GEMM_SHAPES[:2]:
+            sec = time_gemm(ofl, M, N, K)
+            tflops = 2.0 * M * N * K / sec / 1e12
+            out["variants"]["gemm_f32"]["shapes"].append(
+                {"M": M, "N": N, "K": K, "us": round(sec * 1e6, 1), "tflops": round(tflops, 2),
+                 "frac_of_fp32_mfma_peak": round(tflops / PEAK_FP32_MFMA_TFLOPS, 4)})
+            log(f"gemm {M}x{N}x{K}: {tflops:.1f} TFLOP/s")
     if not args.skip_cpu_baseline:
         out["cpu_program"] = cpu_program(ofl, arrays, args.oracle_iters)
     print(json.dumps(out), flush=True)

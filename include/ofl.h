@@ -196,14 +196,15 @@ int ofl_jacobi_run(ofl_grid *g, int iters, float omega, double *gosa_out);
 /* ofl_jacobi_run for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): it
  * calls no hipMalloc, hipFree, event or graph creation. It runs the fused
- * iteration (see ofl_set_fusion) with the sweep's per-wave residual partials in
- * a library-owned device array of 2^19 FP64 slots (4 MiB per device, held
- * until the process ends) instead of a buffer the library allocates; results
+ * iteration (see ofl_set_fusion) with the sweep's per-wave residual partials
+ * (two buffers: even and odd iterations) in a library-owned device array of
+ * 2^19 FP64 slots (4 MiB per device, held until the process ends) instead of a
+ * buffer the library allocates; results
  * are bitwise those of ofl_jacobi_run on the same grid and tile. Preconditions,
  * each refused before any work: the grid is resident (ofl_data_enter done,
  * ESTATE otherwise), gene 111 with hoisted transfers and whole nests (ENOTSUP),
  * OFL_FUSE_RESIDUAL set (ENOTSUP), profiling off (ENOTSUP), not inside a batch
- * (ESTATE), and a sweep of at most 2^19 waves for the grid's tile (EINVAL: a
+ * (ESTATE), and a sweep of at most 2^18 waves for the grid's tile (EINVAL: a
  * tile with longer k-chunks needs fewer). Every call on one
  * device shares that array, so calls that overlap in time on one device (two
  * host threads, or two streams) race and give wrong residuals; serialise them.
@@ -232,7 +233,9 @@ int ofl_data_exit(ofl_grid *g);
  * nest runs on the GPU (gene 111) with hoisted transfers, the sweep can also
  * produce the residual (OFL_FUSE_RESIDUAL: the residual nest's own terms,
  * (wrk2 - p) in FP32 squared and summed in FP64, one partial per wave, then a
- * fixed-order sum), and the copy-back can become an exchange of the p and wrk2
+ * fixed-order sum; the sum of one iteration's partials runs in the first
+ * work-group of the next iteration's sweep launch, the last iteration's after
+ * the loop), and the copy-back can become an exchange of the p and wrk2
  * device buffers (OFL_FUSE_COPYBACK_SWAP: exact, because the sweep writes only
  * the interior and wrk2's device copy first receives p's boundary). Results
  * equal the unfused path's up to the residual's summation order; wrk2's device
@@ -299,7 +302,10 @@ typedef struct ofl_stats {
 /* Profiling on: each GPU nest is bracketed by HIP events on the grid's stream
  * and its time is added to kernel_ms at the next synchronisation. A nest split
  * into regions is bracketed as a whole; under the per-iteration placement it is
- * not timed, since its transfers sit between its launches. */
+ * not timed, since its transfers sit between its launches. In fused runs the
+ * copy-back exchange launches nothing and the residual sums of all iterations
+ * but the last run inside the next sweep launch, so the residual is timed once
+ * per run. */
 int ofl_set_profiling(ofl_grid *g, int on);
 
 /* Which nests profiling brackets (bit n: nest n, as in the offload mask;

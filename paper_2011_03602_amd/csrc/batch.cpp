@@ -246,7 +246,9 @@ void batch_build_tables(ofl_batch *b) {
         frange[2 * static_cast<size_t>(sitems[w].grid)] = static_cast<long long>(w) * b->tile.rows;
     for (size_t w = 0; w < sitems.size(); ++w)
         frange[2 * static_cast<size_t>(sitems[w].grid) + 1] = static_cast<long long>(w + 1) * b->tile.rows;
-    hip_check(hipMalloc(&b->d_fparts, sizeof(double) * std::max<size_t>(1, sitems.size() * b->tile.rows)),
+    // two buffers (even and odd iterations), each one partial per sweep wave
+    b->fparts_len = static_cast<long long>(sitems.size()) * b->tile.rows;
+    hip_check(hipMalloc(&b->d_fparts, sizeof(double) * std::max<size_t>(1, 2 * static_cast<size_t>(b->fparts_len))),
               "hipMalloc(batch fused partials)");
     upload(b->d_frange, frange, s);
     upload(b->d_sitems, sitems, s);
@@ -299,11 +301,22 @@ void batch_enqueue(ofl_batch *b, int iters, float omega) {
     const int vec = b->tile.vec;
     for (int it = 0; it < iters; ++it) {
         const GridView *views = (swap && (it & 1)) ? views_odd : views_even;
+        // fused residual: iteration it writes partial buffer it % 2, and the
+        // first work-groups of its sweep sum the previous iteration's buffer
+        // into each grid's gosa; the last iteration's is summed after the loop
+        double *cur = fuse_r ? fparts + (it & 1) * b->fparts_len : nullptr;
+        PrevParts prev;
+        if (fuse_r && it > 0) {
+            prev.parts = fparts + ((it - 1) & 1) * b->fparts_len;
+            prev.range = frange;
+            prev.ngrids = n;
+        }
         if (b->s_cnt > 0)
             launch_batch_sweep(views, sitems, b->s_cnt, b->tile, b->fmt != OFL_COEF_F32, omega,
-                               blocks_for(b, b->s_cnt), b->stream, fuse_r ? fparts : nullptr);
+                               blocks_for(b, b->s_cnt), b->stream, cur, prev);
         if (fuse_r) {
-            launch_batch_finalize_parts(views, fparts, frange, n, omega, b->stream);
+            if (it == iters - 1)
+                launch_batch_finalize_parts(views, cur, frange, n, omega, b->stream);
         } else {
             if (b->r_cnt > 0)
                 launch_batch_residual(views, ritems, b->r_cnt, vec, b->sum_mode, b->tile.flags,

@@ -20,7 +20,8 @@ struct ofl_batch {
     bool tables_ready = false;
     void *d_views = nullptr;          // views as the grids hold them (even iterations)
     void *d_views_swapped = nullptr;  // p and wrk2 exchanged (odd iterations of a swapping run)
-    void *d_fparts = nullptr;         // fused residual: one partial per sweep wave
+    void *d_fparts = nullptr;         // fused residual: two buffers (even, odd iterations) of one partial per sweep wave
+    long long fparts_len = 0;         // partials per buffer
     void *d_frange = nullptr;         // per grid, its range of d_fparts (ngrids + 1 entries)
     void *d_sitems = nullptr;
     void *d_ritems = nullptr;

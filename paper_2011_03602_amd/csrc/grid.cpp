@@ -473,26 +473,31 @@ namespace {
 // outside the interior only p's own values. The three nests still count as
 // executed on the GPU.
 //
-// static_parts != nullptr: the per-wave partials go there (at least
+// The partials are double-buffered: iteration it writes buffer it % 2, and
+// the first work-group of its sweep sums buffer (it - 1) % 2, the previous
+// iteration's, into gosa before its own march, so no iteration launches a
+// reduction kernel of its own; the last iteration's is summed after the loop.
+//
+// static_parts != nullptr: the partials go there (at least twice
 // sweep_waves() slots, checked by the caller) and nothing is allocated.
 void run_fused(ofl_grid *g, int iters, float omega, double *static_parts = nullptr) {
     grid_ensure_device(g);
     std::vector<Xfer> xs;
     const bool fuse_r = (g->fusion & OFL_FUSE_RESIDUAL) != 0;
     const bool swap = (g->fusion & OFL_FUSE_COPYBACK_SWAP) != 0;
+    const long long need = fuse_r ? sweep_waves(g->I, g->J, g->K, g->tile) : 0;
     double *parts = static_parts;
     if (fuse_r && !static_parts) {
-        const long long need = sweep_waves(g->I, g->J, g->K, g->tile);
-        if (need > g->fused_parts_cap) {
+        if (2 * need > g->fused_parts_cap) {
             grid_sync(g);
             if (g->fused_parts)
                 hip_check(hipFree(g->fused_parts), "hipFree(fused partials)");
             g->fused_parts = nullptr;
             g->fused_parts_cap = 0;
             void *ptr = nullptr;
-            hip_check(hipMalloc(&ptr, sizeof(double) * static_cast<size_t>(need)), "hipMalloc(fused partials)");
+            hip_check(hipMalloc(&ptr, sizeof(double) * static_cast<size_t>(2 * need)), "hipMalloc(fused partials)");
             g->fused_parts = static_cast<double *>(ptr);
-            g->fused_parts_cap = need;
+            g->fused_parts_cap = 2 * need;
         }
         parts = g->fused_parts;
     }
@@ -502,17 +507,25 @@ void run_fused(ofl_grid *g, int iters, float omega, double *static_parts = nullp
         grid_exec(g, xs);
         if (swap)
             grid_sync_wrk2_boundary(g);
+        double *cur = fuse_r ? parts + (it & 1) * need : nullptr;
+        PrevParts prev;
+        if (fuse_r && it > 0) {
+            prev.parts = parts + ((it - 1) & 1) * need;
+            prev.n = need;
+        }
         prof_begin(g, kS);
-        launch_sweep(g->view, g->tile, g->fmt != OFL_COEF_F32, omega, g->stream, fuse_r ? parts : nullptr);
+        launch_sweep(g->view, g->tile, g->fmt != OFL_COEF_F32, omega, g->stream, cur, prev);
         prof_end(g);
         g->stats.gpu_nests[kS] += 1;
         xs.clear();
         plan_after(it, kS, true, OFL_XFER_HOISTED, g->valid, xs);
         if (fuse_r) {
-            prof_begin(g, kR);
-            launch_finalize(parts, sweep_waves(g->I, g->J, g->K, g->tile), omega, g->view.gosa, g->stream,
-                            g->view.partials, kResidualBlocks);
-            prof_end(g);
+            // this iteration's terms are in `cur`; the next sweep sums them
+            if (it == iters - 1) {
+                prof_begin(g, kR);
+                launch_finalize(cur, need, omega, g->view.gosa, g->stream, g->view.partials, kResidualBlocks);
+                prof_end(g);
+            }
         } else {
             prof_begin(g, kR);
             launch_residual(g->view, g->tile.vec, g->sum_mode, g->tile.flags, omega, g->stream);
@@ -1094,7 +1107,8 @@ int ofl_jacobi_run_static(ofl_grid *g, int iters, float omega, double *gosa_out)
             fail(OFL_ENOTSUP, "ofl_jacobi_run_static runs the fused residual: set OFL_FUSE_RESIDUAL (ofl_set_fusion)");
         if (g->profiling)
             fail(OFL_ENOTSUP, "profiling creates HIP events; switch it off for ofl_jacobi_run_static");
-        const long long need = sweep_waves(g->I, g->J, g->K, g->tile);
+        // two buffers of one partial per sweep wave
+        const long long need = 2 * sweep_waves(g->I, g->J, g->K, g->tile);
         if (need > kStaticScratchParts)
             fail(OFL_EINVAL, "the grid's sweep needs " + std::to_string(need) +
                                  " residual partials, more than the static scratch holds (" +

@@ -424,6 +424,42 @@ __device__ __forceinline__ void sweep_march(const GridView &g, int ts, int fixed
     }
 }
 
+// Fixed-order sum of n FP64 values by one whole work-group of any size (a
+// multiple of 64 threads, at most 512): thread t adds x[t], x[t + size], ... in
+// order, each wave folds its lanes by a butterfly, and thread 0 adds the waves
+// in index order. The total is returned on thread 0. Every thread of the
+// work-group must call it (it holds two barriers).
+__device__ __forceinline__ double group_sum_fixed(const double *x, long long n) {
+    __shared__ double wsum[512 / kWave];
+    const long long step = blockDim.x;
+    long long t = threadIdx.x;
+    double v = 0.0;
+    // eight loads in flight, added in index order
+    for (; t + 7 * step < n; t += 8 * step) {
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            a[u] = x[t + u * step];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            v += a[u];
+    }
+    for (; t < n; t += step)
+        v += x[t];
+#pragma unroll
+    for (int m = kWave / 2; m >= 1; m >>= 1)
+        v += __shfl_xor(v, m, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0)
+        wsum[threadIdx.x / kWave] = v;
+    __syncthreads();
+    double total = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < static_cast<int>(blockDim.x / kWave); ++w)
+            total += wsum[w];
+    __syncthreads();  // wsum may be reused by the caller's next call
+    return total;
+}
+
 // Lines a wave may own and the extent of its march, per march axis.
 template <int FLAGS>
 __device__ __forceinline__ void march_extent(const GridView &g, int &fixed_last, int &march_end) {
@@ -434,8 +470,17 @@ __device__ __forceinline__ void march_extent(const GridView &g, int &fixed_last,
 
 template <int VEC, bool BF16, int FLAGS>
 __global__ __launch_bounds__(512) void sweep_kernel(GridView g, int chunk, int nti, int nfb, float omega,
-                                                    int order, double *parts) {
+                                                    int order, double *parts, PrevParts prev) {
     const int bid = static_cast<int>(blockIdx.x);
+    if constexpr ((FLAGS & kFlagFuseResidual) != 0) {
+        // the previous iteration's residual, before this work-group's march
+        // (whole work-group: no wave has returned yet)
+        if (prev.parts && bid == 0) {
+            const double total = group_sum_fixed(prev.parts, prev.n);
+            if (threadIdx.x == 0)
+                *g.gosa = total / (static_cast<double>(omega) * static_cast<double>(omega));
+        }
+    }
     const int L = order == kOrderBand    ? xcd_band(bid, nti * nfb)
                   : order == kOrderRemap ? xcd_remap(bid, gridDim.x)
                                          : bid;
@@ -507,8 +552,20 @@ __device__ __forceinline__ void batch_sweep_item(const GridView &g, const SweepI
 template <int VEC, bool BF16, int FLAGS>
 __global__ __launch_bounds__(512) void batch_sweep_kernel(const GridView *__restrict__ views,
                                                           const SweepItem *__restrict__ items, int nitems,
-                                                          int chunk, float omega, int remap, double *parts) {
+                                                          int chunk, float omega, int remap, double *parts,
+                                                          PrevParts prev) {
     constexpr bool kFuseR = (FLAGS & kFlagFuseResidual) != 0;
+    if constexpr (kFuseR) {
+        // the previous iteration's residual of grid b, by work-group b (and
+        // b + gridDim.x, ...), before any of its items
+        if (prev.parts)
+            for (int b = static_cast<int>(blockIdx.x); b < prev.ngrids; b += gridDim.x) {
+                const long long lo = prev.range[2 * b];
+                const double total = group_sum_fixed(prev.parts + lo, prev.range[2 * b + 1] - lo);
+                if (threadIdx.x == 0)
+                    *views[b].gosa = total / (static_cast<double>(omega) * static_cast<double>(omega));
+            }
+    }
     const int lines = blockDim.x / kWave;
     const int wave = static_cast<int>(threadIdx.x / kWave);
     const int first = remap ? xcd_remap(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x);
@@ -945,25 +1002,27 @@ void check_launch(const char *what) { hip_check(hipGetLastError(), what); }
 namespace {
 
 // Launcher tables over (vec, format, flags): one instantiation per combination.
-using SweepLaunch = void (*)(const GridView &, const TileCfg &, float, int, int, int, double *, hipStream_t);
+using SweepLaunch = void (*)(const GridView &, const TileCfg &, float, int, int, int, double *, const PrevParts &,
+                             hipStream_t);
 using BatchSweepLaunch = void (*)(const GridView *, const SweepItem *, int, const TileCfg &, float, int, double *,
-                                  hipStream_t);
+                                  const PrevParts &, hipStream_t);
 
 template <int VEC, bool BF16, int FLAGS>
 void sweep_one(const GridView &g, const TileCfg &t, float omega, int nti, int nfb, int blocks, double *parts,
-               hipStream_t s) {
+               const PrevParts &prev, hipStream_t s) {
     // bands need whole k-chunks of a multiple of 8 tiles (blocks = nti*nfb*nmc)
     const int order = (t.flags & OFL_TILE_XCD_REMAP) ? kOrderRemap
                       : ((nti * nfb) % kXcds == 0) ? kOrderBand
                                                    : kOrderPlain;
-    sweep_kernel<VEC, BF16, FLAGS><<<blocks, kWave * t.rows, 0, s>>>(g, t.kchunk, nti, nfb, omega, order, parts);
+    sweep_kernel<VEC, BF16, FLAGS><<<blocks, kWave * t.rows, 0, s>>>(g, t.kchunk, nti, nfb, omega, order, parts,
+                                                                       prev);
 }
 
 template <int VEC, bool BF16, int FLAGS>
 void batch_sweep_one(const GridView *views, const SweepItem *items, int nitems, const TileCfg &t, float omega,
-                     int blocks, double *parts, hipStream_t s) {
+                     int blocks, double *parts, const PrevParts &prev, hipStream_t s) {
     batch_sweep_kernel<VEC, BF16, FLAGS><<<blocks, kWave * t.rows, 0, s>>>(
-        views, items, nitems, t.kchunk, omega, (t.flags & OFL_TILE_XCD_REMAP) ? 1 : 0, parts);
+        views, items, nitems, t.kchunk, omega, (t.flags & OFL_TILE_XCD_REMAP) ? 1 : 0, parts, prev);
 }
 
 template <int VEC, bool BF16, int... F>
@@ -1023,14 +1082,17 @@ BatchSweepLaunch batch_sweep_launcher(int vec, bool bf16, int flags) {
 
 }  // namespace
 
-void launch_sweep(const GridView &g, const TileCfg &t, int bf16, float omega, hipStream_t s, double *fused_parts) {
+void launch_sweep(const GridView &g, const TileCfg &t, int bf16, float omega, hipStream_t s, double *fused_parts,
+                  const PrevParts &prev) {
     int nti, nfb, nmc;
     sweep_shape(g.I, g.J, g.K, t, &nti, &nfb, &nmc);
     const long long blocks = static_cast<long long>(nti) * nfb * nmc;
     if (blocks > 0x7fffffffLL)
         fail(OFL_EINVAL, "sweep launch too large for this tile");
     const int flags = (t.flags & kTemplateFlagMask) | (fused_parts ? kFlagFuseResidual : 0);
-    sweep_launcher(t.vec, bf16 != 0, flags)(g, t, omega, nti, nfb, static_cast<int>(blocks), fused_parts, s);
+    if (prev.parts && !fused_parts)
+        fail(OFL_EINVAL, "a folded residual reduction needs the fused sweep");
+    sweep_launcher(t.vec, bf16 != 0, flags)(g, t, omega, nti, nfb, static_cast<int>(blocks), fused_parts, prev, s);
     check_launch("sweep kernel launch");
 }
 
@@ -1051,9 +1113,12 @@ void launch_finalize(const double *partials, long long n, float omega, double *g
 }
 
 void launch_batch_sweep(const GridView *views, const SweepItem *items, int nitems, const TileCfg &t, int bf16,
-                        float omega, int grid_blocks, hipStream_t s, double *fused_parts) {
+                        float omega, int grid_blocks, hipStream_t s, double *fused_parts, const PrevParts &prev) {
     const int flags = (t.flags & kTemplateFlagMask) | (fused_parts ? kFlagFuseResidual : 0);
-    batch_sweep_launcher(t.vec, bf16 != 0, flags)(views, items, nitems, t, omega, grid_blocks, fused_parts, s);
+    if (prev.parts && !fused_parts)
+        fail(OFL_EINVAL, "a folded residual reduction needs the fused sweep");
+    batch_sweep_launcher(t.vec, bf16 != 0, flags)(views, items, nitems, t, omega, grid_blocks, fused_parts, prev,
+                                                  s);
     check_launch("batched sweep kernel launch");
 }
 

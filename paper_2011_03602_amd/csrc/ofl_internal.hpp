@@ -116,10 +116,22 @@ __host__ __device__ inline long long packed_nseg(int J, int pitch, int vec) {
 // Sweep decomposition of a grid: i-tiles, blocks of owned lines, march chunks.
 void sweep_shape(int I, int J, int K, const TileCfg &t, int *nti, int *nfb, int *nmc);
 
+// The previous iteration's fused-residual partials, reduced inside the next
+// fused sweep launch instead of by kernels of their own: the launch's first
+// work-group (a single grid: n partials) or work-groups 0..ngrids-1 (a batch:
+// grid b owns parts[range[2b], range[2b+1])) sum them in a fixed order into
+// gosa before their own march. parts == nullptr: nothing to reduce.
+struct PrevParts {
+    const double *parts = nullptr;
+    long long n = 0;
+    const long long *range = nullptr;
+    int ngrids = 0;
+};
+
 // Single-grid launches (kernels.hip).
 // fused_parts != nullptr: fuse the residual, one partial per wave (sweep_waves() of them).
 void launch_sweep(const GridView &g, const TileCfg &t, int bf16, float omega, hipStream_t s,
-                  double *fused_parts = nullptr);
+                  double *fused_parts = nullptr, const PrevParts &prev = PrevParts{});
 long long sweep_waves(int I, int J, int K, const TileCfg &t);
 // gosa = sum(partials[0..n)) / omega^2 in a fixed order; with scratch (at
 // least scratch_len doubles) large n is summed in two stages.
@@ -147,7 +159,8 @@ void launch_stream(const float *const *src32, int n32, const uint16_t *const *sr
 // Batched launches (kernels.hip).
 // fused_parts != nullptr: fuse the residual, rows partials per item (slot item*rows + wave).
 void launch_batch_sweep(const GridView *views, const SweepItem *items, int nitems, const TileCfg &t, int bf16,
-                        float omega, int grid_blocks, hipStream_t s, double *fused_parts = nullptr);
+                        float omega, int grid_blocks, hipStream_t s, double *fused_parts = nullptr,
+                        const PrevParts &prev = PrevParts{});
 void launch_batch_finalize_parts(const GridView *views, const double *parts, const long long *range, int ngrids,
                                  float omega, hipStream_t s);
 void launch_batch_residual(const GridView *views, const RowItem *items, int nitems, int vec, int sum_mode, int flags,

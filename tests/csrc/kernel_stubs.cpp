@@ -10,7 +10,7 @@ namespace {
 [[noreturn]] void no_device() { fail(OFL_EDEVICE, "this build has no device code"); }
 }  // namespace
 
-void launch_sweep(const GridView &, const TileCfg &, int, float, hipStream_t, double *) { no_device(); }
+void launch_sweep(const GridView &, const TileCfg &, int, float, hipStream_t, double *, const PrevParts &) { no_device(); }
 void launch_finalize(const double *, long long, float, double *, hipStream_t, double *, int) { no_device(); }
 void launch_residual(const GridView &, int, int, int, float, hipStream_t, bool) { no_device(); }
 void launch_copyback(const GridView &, int, int, hipStream_t, bool, bool, float) { no_device(); }
@@ -22,7 +22,7 @@ void launch_stream(const float *const *, int, const uint16_t *const *, int, floa
     no_device();
 }
 void launch_batch_sweep(const GridView *, const SweepItem *, int, const TileCfg &, int, float, int, hipStream_t,
-                        double *) {
+                        double *, const PrevParts &) {
     no_device();
 }
 void launch_batch_finalize_parts(const GridView *, const double *, const long long *, int, float, hipStream_t) {

@@ -6,7 +6,7 @@
 
 namespace ofl {
 
-void launch_sweep(const GridView &, const TileCfg &, int, float, hipStream_t, double *) {}
+void launch_sweep(const GridView &, const TileCfg &, int, float, hipStream_t, double *, const PrevParts &) {}
 void launch_finalize(const double *, long long, float, double *, hipStream_t, double *, int) {}
 void launch_residual(const GridView &, int, int, int, float, hipStream_t, bool) {}
 void launch_copyback(const GridView &, int, int, hipStream_t, bool, bool, float) {}
@@ -16,7 +16,7 @@ void launch_fill_zero(void *, size_t, hipStream_t) {}
 void launch_copy(void *, const void *, size_t, hipStream_t) {}
 void launch_stream(const float *const *, int, const uint16_t *const *, int, float *, size_t, hipStream_t) {}
 void launch_batch_sweep(const GridView *, const SweepItem *, int, const TileCfg &, int, float, int, hipStream_t,
-                        double *) {}
+                        double *, const PrevParts &) {}
 void launch_batch_finalize_parts(const GridView *, const double *, const long long *, int, float, hipStream_t) {}
 void launch_batch_residual(const GridView *, const RowItem *, int, int, int, int, int, hipStream_t) {}
 void launch_batch_finalize(const GridView *, const int *, int, float, hipStream_t) {}

@@ -404,7 +404,10 @@ def test_profiling_only_the_chosen_nests(setup):
     ofl.ofl_reset_stats(g.handle)
     ofl.ofl_set_profiled_nests(g.handle, ofl.OFL_MASK_ALL_GPU)
     ofl.ofl_jacobi_run(g.handle, 2, OMEGA)
-    assert list(ofl.ofl_get_stats(g.handle).timed_nests) == [2, 2, 0 if setup == "fused" else 2]
+    # fused: each iteration's residual sum but the last runs inside the next
+    # sweep launch, so one residual reduction per run is timed on its own
+    want = [2, 1, 0] if setup == "fused" else [2, 2, 2]
+    assert list(ofl.ofl_get_stats(g.handle).timed_nests) == want
     g.close()
 
 

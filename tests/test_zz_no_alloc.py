@@ -94,7 +94,7 @@ def test_static_refuses_without_a_data_region():
 
 def test_static_refuses_a_sweep_beyond_the_scratch():
     # 66x515x514 with one-point, one-row, one-plane tiles: 2 x 513 x 512 = 525,312
-    # waves, just over the 2^19 partials the array holds
+    # waves, two buffers of one partial each: more than the 2^19 the array holds
     shape = (66, 515, 514)
     say("static scratch limit", shape)
     a = {n: np.full(shape[::-1], 0.01, np.float32) for n in ofl.ARRAY_NAMES}
