@@ -421,6 +421,7 @@ typedef struct ofl_tune_result {
     double best_ms;     /* median time of probe_iters iterations with the best tile */
     int evaluated;      /* distinct genes measured */
     int rejected;       /* genes that could not be built or gave wrong results */
+    int from_cache;     /* of the evaluated genes, those whose time came from the tune cache file */
 } ofl_tune_result;
 
 /* Search sweep tiles for one grid (or for a batch) with a GA: genes are bit
@@ -432,6 +433,24 @@ typedef struct ofl_tune_result {
  * best tile is also applied to the grid/batch. p is restored on return. */
 int ofl_grid_tune(ofl_grid *g, const ofl_ga_params *ga, ofl_tune_result *out);
 int ofl_batch_tune(ofl_batch *b, const ofl_ga_params *ga, ofl_tune_result *out);
+
+/* Measurements kept across searches (checkpoint and resume of a tile search;
+ * not a paper passage: the method measures every pattern, and this keeps
+ * those measurements). With a path set, ofl_grid_tune and ofl_batch_tune read
+ * the file's earlier measurements before searching and append every gene they
+ * measure as soon as it is measured, one text line each:
+ *   ofl-tune 1 <key> <gene in hex> <ms, inf (wrong result) or nan (not built)>
+ * The key names what a gene's time depends on besides the gene: grid shapes,
+ * coefficient format, summation mode, fusion, row alignment, probe_iters,
+ * repeats, tolerance, the device (architecture and compute units) and a hash
+ * of the library's sources. A gene found under the search's key is not
+ * measured again (ofl_tune_result.from_cache counts them), so a stopped search
+ * resumes where it stopped and a search with other GA parameters reuses what
+ * was measured. Lines under other keys are kept and ignored. path NULL (the
+ * default) keeps no file. Process-wide; the path is read when a tuner starts.
+ * A file that cannot be opened for appending makes that tuner call fail
+ * (EINVAL) before any measurement. EINVAL for a path holding a newline. */
+int ofl_set_tune_cache(const char *path);
 
 /* The GA of Sec. 4.2.2 over arbitrary bit genes with a caller-supplied
  * measurement: the initial population is random (seed_gene joins it), each

@@ -97,7 +97,7 @@ class OflGaParams(ctypes.Structure):
 
 class OflTuneResult(ctypes.Structure):
     _fields_ = [("best", OflTile), ("best_ms", ctypes.c_double), ("evaluated", ctypes.c_int),
-                ("rejected", ctypes.c_int)]
+                ("rejected", ctypes.c_int), ("from_cache", ctypes.c_int)]
 
 
 class OflGaResult(ctypes.Structure):
@@ -171,6 +171,7 @@ _SIGS = {
     "ofl_batch_get_tile": ([ctypes.c_void_p, ctypes.POINTER(OflTile)], ctypes.c_int),
     "ofl_batch_set_fusion": ([ctypes.c_void_p, ctypes.c_uint], ctypes.c_int),
     "ofl_batch_run": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "ofl_set_tune_cache": ([ctypes.c_char_p], ctypes.c_int),
     "ofl_grid_tune": ([ctypes.c_void_p, ctypes.POINTER(OflGaParams), ctypes.POINTER(OflTuneResult)], ctypes.c_int),
     "ofl_batch_tune": ([ctypes.c_void_p, ctypes.POINTER(OflGaParams), ctypes.POINTER(OflTuneResult)], ctypes.c_int),
     "ofl_ga_search": ([ctypes.c_int, ctypes.POINTER(OflGaParams), ctypes.c_uint32, OFL_GENE_EVAL, ctypes.c_void_p,
@@ -413,6 +414,10 @@ def ofl_batch_run(b, iters: int, omega: float, n_grids: int):
 def ga_params(population=16, generations=12, seed=2011036020, crossover=0.9, mutation=0.05, elite=1,
               probe_iters=5, repeats=3, tolerance=1e-5) -> OflGaParams:
     return OflGaParams(population, generations, seed, crossover, mutation, elite, probe_iters, repeats, tolerance)
+
+
+def ofl_set_tune_cache(path: Optional[str]) -> None:
+    _check(lib().ofl_set_tune_cache(os.fsencode(path) if path is not None else None))
 
 
 def ofl_grid_tune(g, ga: Optional[OflGaParams] = None) -> OflTuneResult:

@@ -8,6 +8,7 @@ library lands next to this file, where the Python binding loads it.
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
 import os
 import subprocess
 import sys
@@ -19,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build", "ofl")
 LIB = os.path.join(HERE, "libofl.so")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "gemm.hip", "grid.cpp", "cpu_nests.cpp", "batch.cpp", "tune.cpp", "blocks.cpp"]
+SOURCES = ["kernels.hip", "gemm.hip", "grid.cpp", "cpu_nests.cpp", "batch.cpp", "tune.cpp", "blocks.cpp", "trace.cpp", "device.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -36,9 +37,21 @@ def _hipcc():
     return "hipcc"
 
 
-def _compile(src: str, verbose: bool) -> str:
+def source_hash() -> str:
+    """First 16 hex digits of a SHA-256 over the library's sources and its
+    header: the build identity the tile tuners' measurement file is keyed on."""
+    h = hashlib.sha256()
+    names = sorted(n for n in os.listdir(CSRC) if n.endswith((".hip", ".cpp", ".hpp")))
+    for path in [os.path.join(CSRC, n) for n in names] + [os.path.join(ROOT, "include", "ofl.h")]:
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _compile(src: str, verbose: bool, defines=()) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc(), "-x", "hip", *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [_hipcc(), "-x", "hip", *COMMON, *defines, "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -53,10 +66,13 @@ def _compile(src: str, verbose: bool) -> str:
 def build(verbose: bool = False, jobs: int = 8) -> str:
     """Compile every source and link libofl.so; returns the library path."""
     os.makedirs(BUILD, exist_ok=True)
+    defines = [f'-DOFL_SOURCE_HASH="{source_hash()}"']
     with cf.ThreadPoolExecutor(max_workers=max(1, min(jobs, len(SOURCES)))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, verbose, defines), SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
+    rocm_lib = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread",
+           f"-L{rocm_lib}", "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{rocm_lib}"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -330,6 +330,7 @@ void batch_enqueue(ofl_batch *b, int iters, float omega) {
 }
 
 void batch_prepare(ofl_batch *b) {
+    TraceRange range("ofl:batch prepare");
     // Hoisted transfers before the loop: every grid's inputs to the device.
     for (ofl_grid *g : b->grids) {
         grid_ensure_device(g);
@@ -366,6 +367,7 @@ void batch_launch(ofl_batch *b, int iters, float omega) {
         b->graph_omega = omega;
         b->graph_fusion = b->fusion;
     }
+    TraceRange range("ofl:batch graph of iterations");
     hip_check(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch");
 }
 

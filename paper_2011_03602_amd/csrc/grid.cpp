@@ -281,7 +281,18 @@ void prof_end(ofl_grid *g) {
 // fold: the residual's finalize step runs inside the copy-back kernel that
 // follows it (both nests on the GPU as whole nests, hoisted transfers), which
 // saves one launch per iteration.
+// Marker-range names: nests by index, transfers by array and direction.
+const char *const kNestRange[3] = {"ofl:gpu sweep", "ofl:gpu residual", "ofl:gpu copy-back"};
+const char *const kCpuNestRange[3] = {"ofl:cpu sweep", "ofl:cpu residual", "ofl:cpu copy-back"};
+const char *const kRegionRange[3] = {"ofl:gpu sweep regions", "ofl:gpu residual regions", "ofl:gpu copy-back regions"};
+const char *const kXferRange[2][14] = {
+    {"ofl:h2d a0", "ofl:h2d a1", "ofl:h2d a2", "ofl:h2d a3", "ofl:h2d b0", "ofl:h2d b1", "ofl:h2d b2", "ofl:h2d c0",
+     "ofl:h2d c1", "ofl:h2d c2", "ofl:h2d bnd", "ofl:h2d wrk1", "ofl:h2d p", "ofl:h2d wrk2"},
+    {"ofl:d2h a0", "ofl:d2h a1", "ofl:d2h a2", "ofl:d2h a3", "ofl:d2h b0", "ofl:d2h b1", "ofl:d2h b2", "ofl:d2h c0",
+     "ofl:d2h c1", "ofl:d2h c2", "ofl:d2h bnd", "ofl:d2h wrk1", "ofl:d2h p", "ofl:d2h wrk2"}};
+
 void gpu_nest(ofl_grid *g, int nest, float omega, bool fold) {
+    TraceRange range(kNestRange[nest]);
     prof_begin(g, nest);
     if (nest == kS) {
         launch_sweep(g->view, g->tile, g->fmt != OFL_COEF_F32, omega, g->stream);
@@ -366,6 +377,7 @@ void xfer_box(ofl_grid *g, int a, int dir, int k0, int k1, int j0, int j1) {
 // `ins` it reads and afterwards copies out the rows of `out` it wrote, and a
 // residual region's sum comes home at once.
 void gpu_nest_regions(ofl_grid *g, int nest, float omega, bool per_iter, const std::vector<int> &ins, int out) {
+    TraceRange range(kRegionRange[nest]);
     const int lev = g->level[nest];
     const int nk = g->K - 2, nj = g->J - 2;
     const long long nreg = lev == OFL_LEVEL_J ? nk : static_cast<long long>(nk) * nj;
@@ -441,6 +453,7 @@ void gpu_nest_regions(ofl_grid *g, int nest, float omega, bool per_iter, const s
 }
 
 void cpu_nest(ofl_grid *g, int nest, float omega) {
+    TraceRange range(kCpuNestRange[nest]);
     if (g->pending)
         grid_sync(g);
     if (nest == kS) {
@@ -502,6 +515,7 @@ void run_fused(ofl_grid *g, int iters, float omega, double *static_parts = nullp
         parts = g->fused_parts;
     }
     for (int it = 0; it < iters; ++it) {
+        TraceRange range("ofl:fused iteration");
         xs.clear();
         plan_before(it, kS, true, OFL_XFER_HOISTED, g->valid, xs);
         grid_exec(g, xs);
@@ -657,7 +671,10 @@ int run_graphed(ofl_grid *g, int from, int iters, float omega) {
         hipGraphExec_t exec = loop_graph(g, n, omega);
         if (!exec)
             break;
-        hip_check(hipGraphLaunch(exec, g->stream), "hipGraphLaunch");
+        {
+            TraceRange range("ofl:graph of iterations");
+            hip_check(hipGraphLaunch(exec, g->stream), "hipGraphLaunch");
+        }
         done += n;
     }
     for (int nest = 0; nest < 3; ++nest) {
@@ -832,6 +849,7 @@ void grid_sync(ofl_grid *g) {
 
 void grid_exec(ofl_grid *g, const std::vector<Xfer> &xs) {
     for (const Xfer &x : xs) {
+        TraceRange range(kXferRange[x.dir != 0 ? 1 : 0][x.array]);
         grid_ensure_device(g);
         const size_t eb = array_elem_bytes(g, x.array);
         const size_t bytes = g->n * eb;

@@ -175,6 +175,18 @@ void launch_gemm_f32(int M, int N, int K, const float *A, int lda, const float *
                      hipStream_t s);
 
 int device_cu_count(int device);
+std::string device_arch(int device);  // e.g. "gfx950:sramecc+:xnack-"
+
+// Host ranges for marker traces (trace.cpp): a range per offloaded nest,
+// planned transfer, graph launch, batched run and tuner measurement.
+void trace_push(const char *name);
+void trace_pop();
+struct TraceRange {
+    explicit TraceRange(const char *name) { trace_push(name); }
+    ~TraceRange() { trace_pop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 // Library-owned device scratch for the entry point that allocates nothing
 // (ofl_jacobi_run_static): kStaticScratchParts FP64 slots per device, held

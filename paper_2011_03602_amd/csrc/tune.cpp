@@ -21,11 +21,17 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <limits>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <numeric>
+#include <sstream>
+#include <string>
 #include <vector>
 
 #include "abi_util.hpp"
@@ -316,7 +322,11 @@ GaOutcome ga_search(const ofl_ga_params &ga, int bits, uint32_t seed_gene, Eval 
         auto it = memo.find(g);
         if (it != memo.end())
             return it->second;
-        double t = evaluate(g);
+        double t;
+        {
+            TraceRange range("ofl:ga measure gene");
+            t = evaluate(g);
+        }
         if (!(t > 0.0 && t < kInf)) {  // NaN (not buildable), inf (wrong), or no positive time
             ++rejected;
             t = kInf;
@@ -379,9 +389,137 @@ GaOutcome ga_search(const ofl_ga_params &ga, int bits, uint32_t seed_gene, Eval 
     return GaOutcome{best, best_t, static_cast<int>(memo.size()), rejected};
 }
 
+// ---- measurements kept across searches (checkpoint and resume)
+//
+// One line per measured gene, appended as soon as it is measured:
+//   ofl-tune 1 <key> <gene, hex> <ms | inf | nan>
+// The key names everything a gene's time depends on besides the gene: the
+// grid shapes and formats, summation mode, fusion, row alignment, the GA's
+// timing and check parameters, the device and the library's sources. A
+// search under the same key takes those times instead of measuring again.
+
+#ifndef OFL_SOURCE_HASH
+#define OFL_SOURCE_HASH "unknown"
+#endif
+
+std::mutex g_cache_mu;
+std::string g_cache_path;  // empty: no file
+
+class TuneCache {
+  public:
+    TuneCache(const std::string &path, std::string key) : key_(std::move(key)) {
+        if (path.empty())
+            return;
+        std::ifstream in(path);  // a missing file is an empty cache
+        std::string line;
+        while (std::getline(in, line)) {
+            std::istringstream ls(line);
+            std::string tag, ver, k, gene_hex, t;
+            if (!(ls >> tag >> ver >> k >> gene_hex >> t) || tag != "ofl-tune" || ver != "1" || k != key_)
+                continue;
+            char *end = nullptr;
+            const unsigned long gene = std::strtoul(gene_hex.c_str(), &end, 16);
+            if (*end != '\0' || gene > 0xffffffffUL)
+                continue;
+            const double v = std::strtod(t.c_str(), &end);
+            if (*end != '\0')
+                continue;
+            known_[static_cast<uint32_t>(gene)] = v;
+        }
+        out_ = std::fopen(path.c_str(), "a");
+        if (!out_)
+            fail(OFL_EINVAL, "tune cache: cannot open " + path + " for appending");
+    }
+    ~TuneCache() {
+        if (out_)
+            std::fclose(out_);
+    }
+    TuneCache(const TuneCache &) = delete;
+    TuneCache &operator=(const TuneCache &) = delete;
+
+    bool lookup(uint32_t gene, double *t) const {
+        auto it = known_.find(gene);
+        if (it == known_.end())
+            return false;
+        *t = it->second;
+        return true;
+    }
+    void record(uint32_t gene, double t) {
+        known_[gene] = t;
+        if (!out_)
+            return;
+        std::fprintf(out_, "ofl-tune 1 %s %x %.17g\n", key_.c_str(), gene, t);
+        std::fflush(out_);
+    }
+
+  private:
+    std::string key_;
+    std::map<uint32_t, double> known_;
+    FILE *out_ = nullptr;
+};
+
+std::string cache_path() {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    return g_cache_path;
+}
+
+std::string device_key(int device) {
+    std::string arch = device_arch(device) + "/" + std::to_string(device_cu_count(device)) + "cu";
+    for (char &c : arch)
+        if (c == ' ' || c == '\t')
+            c = '_';
+    return arch;
+}
+
+std::string ga_key(const ofl_ga_params &ga) {
+    char buf[96];
+    std::snprintf(buf, sizeof buf, "probe%d;rep%d;tol%.6g", ga.probe_iters, ga.repeats, ga.tolerance);
+    return buf;
+}
+
+std::string grid_key(const ofl_grid *g, const ofl_ga_params &ga) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "grid;%dx%dx%d;fmt%d;sum%d;fuse%u;align%d;", g->I, g->J, g->K, g->fmt, g->sum_mode,
+                  g->fusion, g->row_align);
+    return buf + ga_key(ga) + ";" + device_key(g->device) + ";" + OFL_SOURCE_HASH;
+}
+
+std::string batch_key(const ofl_batch *b, const ofl_ga_params &ga) {
+    // the grids' shapes and alignments, in batch order, hashed (FNV-1a, 64 bits)
+    uint64_t h = 1469598103934665603ULL;
+    auto mix = [&](int v) {
+        for (int s = 0; s < 32; s += 8) {
+            h ^= static_cast<uint64_t>((static_cast<unsigned>(v) >> s) & 0xffu);
+            h *= 1099511628211ULL;
+        }
+    };
+    for (const ofl_grid *g : b->grids) {
+        mix(g->I);
+        mix(g->J);
+        mix(g->K);
+        mix(g->row_align);
+    }
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "batch;n%zu;shapes%016llx;fmt%d;sum%d;fuse%u;", b->grids.size(),
+                  static_cast<unsigned long long>(h), b->fmt, b->sum_mode, b->fusion);
+    return buf + ga_key(ga) + ";" + device_key(b->device) + ";" + OFL_SOURCE_HASH;
+}
+
 template <class Eval>
-void run_ga(const ofl_ga_params &ga, bool batch, uint32_t seed_gene, Eval &&evaluate, ofl_tune_result *out) {
-    const GaOutcome r = ga_search(ga, gene_bits(batch), seed_gene, evaluate);
+void run_ga(const ofl_ga_params &ga, bool batch, uint32_t seed_gene, TuneCache &cache, Eval &&evaluate,
+            ofl_tune_result *out) {
+    int from_cache = 0;
+    auto cached_eval = [&](uint32_t gene) -> double {
+        double t;
+        if (cache.lookup(gene, &t)) {
+            ++from_cache;
+            return t;
+        }
+        t = evaluate(gene);
+        cache.record(gene, t);
+        return t;
+    };
+    const GaOutcome r = ga_search(ga, gene_bits(batch), seed_gene, cached_eval);
     TileCfg t;
     if (!(r.best_t < kInf) || !decode(r.best, batch, &t))
         fail(OFL_ESTATE, "no gene produced a correct result");
@@ -389,6 +527,7 @@ void run_ga(const ofl_ga_params &ga, bool batch, uint32_t seed_gene, Eval &&eval
     out->best_ms = r.best_t;
     out->evaluated = r.evaluated;
     out->rejected = r.rejected;
+    out->from_cache = from_cache;
 }
 
 ofl_ga_params defaults_or(const ofl_ga_params *ga) {
@@ -657,6 +796,16 @@ int ofl_grid_search_loops(ofl_grid *g, const ofl_ga_params *ga_in, int iters, fl
     });
 }
 
+int ofl_set_tune_cache(const char *path) {
+    return guarded(nullptr, [&] {
+        std::string p = path ? path : "";
+        if (p.find('\n') != std::string::npos)
+            fail(OFL_EINVAL, "tune cache path holds a newline");
+        std::lock_guard<std::mutex> lock(g_cache_mu);
+        g_cache_path = p;
+    });
+}
+
 int ofl_grid_tune(ofl_grid *g, const ofl_ga_params *ga_in, ofl_tune_result *out) {
     return grid_call(g, [&] {
         if (!g || !out)
@@ -695,7 +844,8 @@ int ofl_grid_tune(ofl_grid *g, const ofl_ga_params *ga_in, ofl_tune_result *out)
         };
         ofl_tune_result res{};
         try {
-            run_ga(ga, false, encode(old, false), evaluate, &res);
+            TuneCache cache(cache_path(), grid_key(g, ga));
+            run_ga(ga, false, encode(old, false), cache, evaluate, &res);
         } catch (...) {
             g->mask = mask;
             g->mode = mode;
@@ -747,7 +897,8 @@ int ofl_batch_tune(ofl_batch *b, const ofl_ga_params *ga_in, ofl_tune_result *ou
             return ms;
         };
         ofl_tune_result res{};
-        run_ga(ga, true, encode(old, true), evaluate, &res);
+        TuneCache cache(cache_path(), batch_key(b, ga));
+        run_ga(ga, true, encode(old, true), cache, evaluate, &res);
         const ofl_tile best = res.best;
         if (ofl_batch_set_tile(b, &best) != OFL_OK)
             fail(OFL_EINVAL, ofl_last_error());

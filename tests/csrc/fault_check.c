@@ -17,6 +17,7 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <unistd.h>
 
 #include "ofl.h"
 
@@ -315,6 +316,66 @@ static int static_case(void) {
     return 0;
 }
 
+/* The tile tuner's measurement file on the stand-in runtime: no kernel runs,
+ * so every gene's check fails and is recorded as a wrong result (inf), one
+ * line per gene; a repeated search reads them all back and appends nothing;
+ * an unwritable path is refused before any measurement. */
+static long count_lines(const char *path) {
+    FILE *f = fopen(path, "r");
+    if (!f)
+        return -1;
+    long n = 0;
+    int c;
+    while ((c = fgetc(f)) != EOF)
+        n += c == '\n';
+    fclose(f);
+    return n;
+}
+
+static int cache_case(void) {
+    char path[512];
+    const char *tmp = getenv("TMPDIR");
+    snprintf(path, sizeof path, "%s/ofl_tune_cache_%ld.txt", tmp && *tmp ? tmp : "/tmp", (long)getpid());
+    remove(path);
+    problem pb;
+    make(&pb, 37, 9, 7);
+    ofl_grid_desc d = desc_of(&pb, OFL_COEF_F32);
+    ofl_grid *g = NULL;
+    CHECK(ofl_grid_create(&d, &g) == OFL_OK);
+    ofl_ga_params ga;
+    memset(&ga, 0, sizeof ga);
+    ga.population = 4;
+    ga.generations = 2;
+    ga.seed = 5;
+    ga.crossover = 0.9;
+    ga.mutation = 0.05;
+    ga.elite = 1;
+    ga.probe_iters = 1;
+    ga.repeats = 1;
+    ga.tolerance = 1e-5;
+    ofl_tune_result r;
+    CHECK(ofl_set_tune_cache(path) == OFL_OK);
+    CHECK(ofl_grid_tune(g, &ga, &r) == OFL_ESTATE); /* no gene gives a right result without kernels */
+    const long n1 = count_lines(path);
+    CHECK(n1 > 0);
+    CHECK(ofl_grid_tune(g, &ga, &r) == OFL_ESTATE);
+    CHECK(count_lines(path) == n1); /* every gene read back, none measured */
+    ga.seed = 6;
+    CHECK(ofl_grid_tune(g, &ga, &r) == OFL_ESTATE);
+    CHECK(count_lines(path) >= n1);
+    char bad[600];
+    snprintf(bad, sizeof bad, "%s.missing-dir/x.txt", path);
+    CHECK(ofl_set_tune_cache(bad) == OFL_OK);
+    CHECK(ofl_grid_tune(g, &ga, &r) == OFL_EINVAL);
+    CHECK(strstr(ofl_last_error(), "tune cache") != NULL);
+    CHECK(ofl_set_tune_cache(NULL) == OFL_OK);
+    CHECK(ofl_set_tune_cache("a\nb") == OFL_EINVAL);
+    ofl_grid_destroy(g);
+    drop(&pb);
+    remove(path);
+    return 0;
+}
+
 int main(void) {
     long calls = 0, total = 0;
     int failed = 0, sticky = 0;
@@ -322,6 +383,8 @@ int main(void) {
     /* the entry point that allocates nothing */
     CHECK(static_case() == 0);
     printf("static-scratch run: no allocating HIP call\n");
+    CHECK(cache_case() == 0);
+    printf("tune cache: written, read back, refused when unwritable\n");
 
     /* grids whose device state exists */
     CHECK(grid_case(0, &total, &failed) == 0 && !failed && total > 40);

@@ -35,6 +35,11 @@ void launch_gemm_f32(int, int, int, const float *, int, const float *, int, floa
     no_device();
 }
 int device_cu_count(int) { no_device(); }
+std::string device_arch(int) { no_device(); }
 double *static_scratch(int) { no_device(); }
+
+// no marker ranges in the host-only builds
+void trace_push(const char *) {}
+void trace_pop() {}
 
 }  // namespace ofl

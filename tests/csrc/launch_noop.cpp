@@ -23,10 +23,15 @@ void launch_batch_finalize(const GridView *, const int *, int, float, hipStream_
 void launch_batch_copyback(const GridView *, const RowItem *, int, int, int, int, hipStream_t, bool) {}
 void launch_gemm_f32(int, int, int, const float *, int, const float *, int, float *, int, hipStream_t) {}
 int device_cu_count(int) { return 256; }
+std::string device_arch(int) { return "stand-in"; }
 // The no-op sweep never writes the partials, so one slot stands for the array.
 double *static_scratch(int) {
     static double slot[1];
     return slot;
 }
+
+// no marker ranges in the host-only builds
+void trace_push(const char *) {}
+void trace_pop() {}
 
 }  // namespace ofl

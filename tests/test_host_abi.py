@@ -387,3 +387,9 @@ def test_eight_point_tiles_are_checked_against_the_layout():
         ofl.ofl_batch_create([g.handle], ofl.tile(vec=8, rows=2, kchunk=2))
     assert e.value.code == ofl.OFL_ENOTSUP
     g.close()
+
+
+def test_library_links_the_marker_api():
+    """The nests, transfers and graph launches are marked with ROCTx ranges."""
+    deps = subprocess.run(["ldd", ofl.LIB_PATH], capture_output=True, text=True).stdout
+    assert "roctx" in deps
