@@ -316,7 +316,7 @@ void batch_enqueue(ofl_batch *b, int iters, float omega) {
                                blocks_for(b, b->s_cnt), b->stream, cur, prev);
         if (fuse_r) {
             if (it == iters - 1)
-                launch_batch_finalize_parts(views, cur, frange, n, omega, b->stream);
+                launch_batch_fold_finalize(views, cur, frange, n, omega, kWave * b->tile.rows, b->stream);
         } else {
             if (b->r_cnt > 0)
                 launch_batch_residual(views, ritems, b->r_cnt, vec, b->sum_mode, b->tile.flags,

@@ -537,7 +537,7 @@ void run_fused(ofl_grid *g, int iters, float omega, double *static_parts = nullp
             // this iteration's terms are in `cur`; the next sweep sums them
             if (it == iters - 1) {
                 prof_begin(g, kR);
-                launch_finalize(cur, need, omega, g->view.gosa, g->stream, g->view.partials, kResidualBlocks);
+                launch_fold_finalize(cur, need, omega, g->view.gosa, kWave * g->tile.rows, g->stream);
                 prof_end(g);
             }
         } else {

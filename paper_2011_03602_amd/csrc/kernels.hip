@@ -790,26 +790,29 @@ __global__ __launch_bounds__(kResidualThreads) void batch_finalize_kernel(const 
     finalize_sum(g.partials, range[blockIdx.x + 1] - range[blockIdx.x], omega, g.gosa);
 }
 
-// Fused batches: grid b sums parts[range[2b] .. range[2b+1]) (its sweep waves).
-__global__ __launch_bounds__(kResidualThreads) void batch_finalize_parts_kernel(const GridView *__restrict__ views,
-                                                                                const double *__restrict__ parts,
-                                                                                const long long *__restrict__ range,
-                                                                                double omega) {
-    __shared__ double sm[kResidualThreads];
-    const long long lo = range[2 * blockIdx.x];
-    const long long hi = range[2 * blockIdx.x + 1];
-    double v = 0.0;
-    for (long long t = lo + threadIdx.x; t < hi; t += kResidualThreads)
-        v += parts[t];
-    sm[threadIdx.x] = v;
-    __syncthreads();
-    for (int h = kResidualThreads / 2; h >= 1; h >>= 1) {
-        if (static_cast<int>(threadIdx.x) < h)
-            sm[threadIdx.x] += sm[threadIdx.x + h];
-        __syncthreads();
-    }
+// The fused residual's last sum, after the last iteration's sweep: the same
+// fixed-order group sum, with the same work-group size, that the next sweep's
+// first work-group(s) apply to every earlier iteration, so the gosa a run
+// returns is computed by that code too. One grid: one work-group over n
+// partials. A batch: work-group b (and b + gridDim.x, ...) sums grid b's
+// range parts[range[2b], range[2b+1]).
+__global__ __launch_bounds__(512) void fold_finalize_kernel(const double *parts, long long n, double omega,
+                                                            double *gosa) {
+    const double total = group_sum_fixed(parts, n);
     if (threadIdx.x == 0)
-        *views[blockIdx.x].gosa = sm[0] / (omega * omega);
+        *gosa = total / (omega * omega);
+}
+
+__global__ __launch_bounds__(512) void batch_fold_finalize_kernel(const GridView *__restrict__ views,
+                                                                  const double *__restrict__ parts,
+                                                                  const long long *__restrict__ range, int ngrids,
+                                                                  double omega) {
+    for (int b = static_cast<int>(blockIdx.x); b < ngrids; b += gridDim.x) {
+        const long long lo = range[2 * b];
+        const double total = group_sum_fixed(parts + lo, range[2 * b + 1] - lo);
+        if (threadIdx.x == 0)
+            *views[b].gosa = total / (omega * omega);
+    }
 }
 
 // ---------------------------------------------------------------- copy-back
@@ -1122,10 +1125,21 @@ void launch_batch_sweep(const GridView *views, const SweepItem *items, int nitem
     check_launch("batched sweep kernel launch");
 }
 
-void launch_batch_finalize_parts(const GridView *views, const double *parts, const long long *range, int ngrids,
-                                 float omega, hipStream_t s) {
-    batch_finalize_parts_kernel<<<ngrids, kResidualThreads, 0, s>>>(views, parts, range, static_cast<double>(omega));
-    check_launch("batched fused finalize launch");
+void launch_fold_finalize(const double *parts, long long n, float omega, double *gosa, int threads, hipStream_t s) {
+    if (threads < kWave || threads > 512 || threads % kWave != 0)
+        fail(OFL_EINVAL, "fused residual sum: work-group size must be 64..512 threads in whole waves");
+    fold_finalize_kernel<<<1, threads, 0, s>>>(parts, n, static_cast<double>(omega), gosa);
+    check_launch("fused residual sum launch");
+}
+
+void launch_batch_fold_finalize(const GridView *views, const double *parts, const long long *range, int ngrids,
+                                float omega, int threads, hipStream_t s) {
+    if (threads < kWave || threads > 512 || threads % kWave != 0)
+        fail(OFL_EINVAL, "fused residual sum: work-group size must be 64..512 threads in whole waves");
+    if (ngrids < 1)
+        return;
+    batch_fold_finalize_kernel<<<ngrids, threads, 0, s>>>(views, parts, range, ngrids, static_cast<double>(omega));
+    check_launch("batched fused residual sum launch");
 }
 
 static int rows_per_wave(int nrt, int blocks) {

@@ -161,8 +161,12 @@ void launch_stream(const float *const *src32, int n32, const uint16_t *const *sr
 void launch_batch_sweep(const GridView *views, const SweepItem *items, int nitems, const TileCfg &t, int bf16,
                         float omega, int grid_blocks, hipStream_t s, double *fused_parts = nullptr,
                         const PrevParts &prev = PrevParts{});
-void launch_batch_finalize_parts(const GridView *views, const double *parts, const long long *range, int ngrids,
-                                 float omega, hipStream_t s);
+// The fused residual's last sum by the group sum the sweeps fold in, with the
+// sweep's work-group size `threads` (64 x tile rows): one grid's n partials
+// into gosa, or each batched grid's range of parts into its gosa.
+void launch_fold_finalize(const double *parts, long long n, float omega, double *gosa, int threads, hipStream_t s);
+void launch_batch_fold_finalize(const GridView *views, const double *parts, const long long *range, int ngrids,
+                                float omega, int threads, hipStream_t s);
 void launch_batch_residual(const GridView *views, const RowItem *items, int nitems, int vec, int sum_mode, int flags,
                            int grid_blocks, hipStream_t s);
 void launch_batch_finalize(const GridView *views, const int *partial_range, int ngrids, float omega,

@@ -25,9 +25,8 @@ void launch_batch_sweep(const GridView *, const SweepItem *, int, const TileCfg 
                         double *, const PrevParts &) {
     no_device();
 }
-void launch_batch_finalize_parts(const GridView *, const double *, const long long *, int, float, hipStream_t) {
-    no_device();
-}
+void launch_fold_finalize(const double *, long long, float, double *, int, hipStream_t) { no_device(); }
+void launch_batch_fold_finalize(const GridView *, const double *, const long long *, int, float, int, hipStream_t) { no_device(); }
 void launch_batch_residual(const GridView *, const RowItem *, int, int, int, int, int, hipStream_t) { no_device(); }
 void launch_batch_finalize(const GridView *, const int *, int, float, hipStream_t) { no_device(); }
 void launch_batch_copyback(const GridView *, const RowItem *, int, int, int, int, hipStream_t, bool) { no_device(); }

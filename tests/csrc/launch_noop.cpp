@@ -17,7 +17,8 @@ void launch_copy(void *, const void *, size_t, hipStream_t) {}
 void launch_stream(const float *const *, int, const uint16_t *const *, int, float *, size_t, hipStream_t) {}
 void launch_batch_sweep(const GridView *, const SweepItem *, int, const TileCfg &, int, float, int, hipStream_t,
                         double *, const PrevParts &) {}
-void launch_batch_finalize_parts(const GridView *, const double *, const long long *, int, float, hipStream_t) {}
+void launch_fold_finalize(const double *, long long, float, double *, int, hipStream_t) {}
+void launch_batch_fold_finalize(const GridView *, const double *, const long long *, int, float, int, hipStream_t) {}
 void launch_batch_residual(const GridView *, const RowItem *, int, int, int, int, int, hipStream_t) {}
 void launch_batch_finalize(const GridView *, const int *, int, float, hipStream_t) {}
 void launch_batch_copyback(const GridView *, const RowItem *, int, int, int, int, hipStream_t, bool) {}

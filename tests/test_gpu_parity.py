@@ -463,6 +463,48 @@ def test_fused_nests_equal_unfused(fusion, iters, fmt):
     g.close()
 
 
+# The fused residual of each iteration but the last is summed by the first
+# work-group of the next sweep, and the last one by a work-group of the same
+# size running the same group sum: work-groups of 1, 3, 5 and 7 waves (not
+# powers of two) and runs long enough to fold several sums.
+@pytest.mark.parametrize("rows", [1, 3, 5, 7])
+def test_fused_residual_sum_at_every_work_group_size(rows):
+    say("fused residual sum, rows", rows)
+    a = synth.make_problem(131, 37, 45, seed=19)
+    t = ofl.tile(vec=4, rows=rows, kchunk=3, flags=1)
+    ref, r_ref = run_gpu(a, 5, tile=t)
+    g = ofl.Grid(a)
+    ofl.ofl_set_tile(g.handle, t)
+    ofl.ofl_set_fusion(g.handle, ofl.OFL_FUSE_RESIDUAL)
+    r = ofl.ofl_jacobi_run(g.handle, 5, OMEGA)
+    assert np.array_equal(g.p, ref.p)
+    assert r == pytest.approx(r_ref, rel=1e-12)
+    check_against_oracle(a, g, r, 5)
+    ref.close()
+    g.close()
+
+
+def test_fused_batch_residual_sum_with_three_wave_work_groups():
+    say("fused batch residual sum, rows 3")
+    probs = _small_batch()
+    tile = ofl.tile(vec=0, rows=3, kchunk=2, flags=1)
+    ref = [ofl.Grid(a) for a in probs]
+    rb = ofl.ofl_batch_create([g.handle for g in ref], tile)
+    r_ref = ofl.ofl_batch_run(rb, 4, OMEGA, len(ref))
+    grids = [ofl.Grid(a) for a in probs]
+    b = ofl.ofl_batch_create([g.handle for g in grids], tile)
+    ofl.ofl_batch_set_fusion(b, ofl.OFL_FUSE_RESIDUAL)
+    r = ofl.ofl_batch_run(b, 4, OMEGA, len(grids))
+    for a, g, gr, x, xr in zip(probs, grids, ref, r, r_ref):
+        assert np.array_equal(g.p, gr.p)
+        assert x == pytest.approx(xr, rel=1e-12)
+        check_against_oracle(a, g, x, 4)
+    ofl.ofl_batch_destroy(b)
+    ofl.ofl_batch_destroy(rb)
+    for g in grids + ref:
+        g.close()
+
+
 def test_fused_runs_hand_over_state_to_unfused_runs_and_cpu_nests():
     say("fusion state handover")
     a = synth.make_problem(70, 41, 33, seed=19)
