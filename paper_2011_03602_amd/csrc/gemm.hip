@@ -6,11 +6,12 @@
 // 128 x 256 tile of C. Each wave owns a 64 x 128 quarter as 2 x 4 accumulator
 // tiles of 32 x 32, updated by v_mfma_f32_32x32x2_f32 (FP32 operands, FP32
 // accumulation); each operand value read from LDS feeds two or four products.
-// Products too small to give every CU two such tiles use 64 x 256 tiles (four
-// waves of 64 x 64 side by side), twice as many. The K dimension advances in stages of 16: the next stage's
-// A and B tiles are fetched from global memory into registers while the
-// current stage, held in LDS, feeds the matrix cores. LDS is double-buffered,
-// so one barrier per stage suffices.
+// Products whose 128-row tiles leave much of their last round of resident
+// work-groups idle use 64 x 256 tiles (four waves of 64 x 64 side by side),
+// twice as many (see launch_gemm_f32). The K dimension advances in stages of
+// 16: the next stage's A and B tiles are fetched from global memory into
+// registers while the current stage, held in LDS, feeds the matrix cores. LDS
+// is double-buffered, so one barrier per stage suffices.
 //
 // Tiles are handed to work-groups so that each XCD works through a contiguous
 // run of them. Measured at 4096^3 with 128 x 128 tiles, this order ran at up
@@ -221,13 +222,49 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_f32_kernel(GemmArgs g, int 
 
 }  // namespace
 
+namespace {
+
+// Work-groups of a tile height resident on one CU at a time (registers and LDS
+// decide: two of the 128-row kernel, three of the 64-row one on gfx950), from
+// the runtime's occupancy query, taken once.
+template <int TM>
+int resident_per_cu() {
+    static const int n = [] {
+        int blocks = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gemm_f32_kernel<TM>, kGemmThreads, 0) != hipSuccess ||
+            blocks < 1)
+            blocks = 1;
+        return blocks;
+    }();
+    return n;
+}
+
+// Fraction of the work-group slots busy over the whole product when `tiles`
+// tiles run in rounds of `slots`: the last round's idle slots are the tail.
+double round_fill(long long tiles, long long slots) {
+    const long long rounds = (tiles + slots - 1) / slots;
+    return static_cast<double>(tiles) / static_cast<double>(rounds * slots);
+}
+
+}  // namespace
+
 void launch_gemm_f32(int M, int N, int K, const float *A, int lda, const float *B, int ldb, float *C, int ldc,
                      hipStream_t s) {
     const GemmArgs g{M, N, K, A, lda, B, ldb, C, ldc};
     const bool aligned = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (reinterpret_cast<uintptr_t>(B) % 16 == 0) &&
                          lda % 4 == 0 && ldb % 4 == 0;
+    // Tile height by the tail of the last round of tiles: the 128-row tiles
+    // reuse each operand more and run about 5% faster in steady state (8192^3:
+    // 141 against 133.5 TFLOP/s), so they are taken unless the 64-row ones fill
+    // the rounds of resident work-groups better by more than that. Measured:
+    // 2048^3 104 against 61 TFLOP/s and 3072^3 99 against 79 for 64 rows,
+    // 4096^3 138 against 109 for 128 rows, and 6144^3 133 for 64 rows against
+    // 105 for 128 (1152 tiles of 128 rows are 2.25 rounds of 512).
     const long long tiles128 = static_cast<long long>((N + kTileN - 1) / kTileN) * ((M + 127) / 128);
-    if (tiles128 >= 2 * kCus) {
+    const long long tiles64 = static_cast<long long>((N + kTileN - 1) / kTileN) * ((M + 63) / 64);
+    const double fill128 = round_fill(tiles128, static_cast<long long>(kCus) * resident_per_cu<128>());
+    const double fill64 = round_fill(tiles64, static_cast<long long>(kCus) * resident_per_cu<64>());
+    if (fill128 >= 0.95 * fill64) {
         const dim3 grid((N + kTileN - 1) / kTileN, (M + 127) / 128);
         hipLaunchKernelGGL(gemm_f32_kernel<128>, grid, dim3(kGemmThreads), 0, s, g, aligned ? 1 : 0);
     } else {

@@ -96,3 +96,19 @@ def test_large_square_sampled():
     a = da[rows].cpu().numpy()
     b = db.cpu().numpy()
     check(a, b, dc[rows].cpu().numpy())
+
+
+# Large ragged products on both tile heights: 4000 x 4000 fills whole rounds of
+# 128-row tiles (512 tiles), 6000 x 6144 fills the rounds of 64-row tiles better
+# (2256 tiles against 1128 in 2.2 rounds); rows near both ends and a tile edge.
+@pytest.mark.parametrize("M,N,K", [(4000, 4000, 257), (6000, 6144, 129)])
+def test_large_ragged_sampled(M, N, K):
+    say("gemm", M, N, K, "sampled rows")
+    g = torch.Generator(device="cuda").manual_seed(M + K)
+    da = torch.rand((M, K), device="cuda", generator=g) * 2 - 1
+    db = torch.rand((K, N), device="cuda", generator=g) * 2 - 1
+    dc = torch.empty((M, N), device="cuda")
+    ofl.ofl_gemm_f32(M, N, K, da.data_ptr(), K, db.data_ptr(), N, dc.data_ptr(), N, None)
+    torch.cuda.synchronize()
+    rows = [0, 63, 64, 127, 128, M // 2 + 1, M - 65, M - 2, M - 1]
+    check(da[rows].cpu().numpy(), db.cpu().numpy(), dc[rows].cpu().numpy())
