@@ -34,3 +34,13 @@ def test_traffic_record_names_its_kernel_source():
     assert set(rec["tile"]) == {"vec", "rows", "kchunk", "flags", "occupancy"}
     assert rec["hbm_bytes_per_launch"] == rec["hbm_read_bytes_per_launch"] + rec["hbm_write_bytes_per_launch"]
     assert rec["algorithmic_bytes_per_launch"] == 56 * 255 * 255 * 511
+
+
+def test_traffic_record_is_for_the_current_kernel_source():
+    """The benchmark reports counter traffic only for the kernel source it was
+    taken on; the committed record must match the committed kernels."""
+    import hashlib
+
+    rec = json.load(open(os.path.join(ROOT, "profiles", "sweep_f32_257x257x513_traffic.json")))
+    src = os.path.join(ROOT, "paper_2011_03602_amd", "csrc", "kernels.hip")
+    assert rec["kernel_source_sha256_16"] == hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
