@@ -72,7 +72,9 @@ bool decode(uint32_t gene, bool batch, TileCfg *t) {
 }
 
 uint32_t encode(const TileCfg &t, bool batch) {
-    uint32_t g = t.vec == 1 ? 0u : (t.vec == 2 ? 1u : (t.vec == 4 ? 2u : 3u));
+    // vector code: 1, 2, 4 (also for a batch's per-grid width, vec 0, which
+    // sets bit 14 and leaves a buildable code below it), 8
+    uint32_t g = t.vec == 1 ? 0u : (t.vec == 2 ? 1u : (t.vec == 8 ? 3u : 2u));
     if (batch && t.vec == 0)
         g |= 1u << 14;
     int r = 0;

@@ -103,3 +103,29 @@ def test_unwritable_cache_fails_before_measuring(tmp_path):
         g.close()
     finally:
         ofl.ofl_set_tune_cache(None)
+
+
+def _seed_time(path, gene):
+    times = [float(r[4]) for r in lines(path) if int(r[3], 16) == gene]
+    assert len(times) == 1, times
+    return times[0]
+
+
+def test_searches_measure_the_tile_they_start_from(cache):
+    """The population starts with the current tile's gene: it must decode back
+    to a buildable tile and be measured (a finite time in the file). The default
+    grid tile (4 points per lane, 4 rows, 2-plane chunks, NT loads and stores)
+    is gene 0x19a; the default batch tile (the same with each grid's own width,
+    1 row, bit 14 set) is gene 0x4192."""
+    g = ofl.Grid(synth.make_problem(200, 21, 19, seed=42))
+    assert ofl.ofl_get_tile(g.handle).as_dict() == dict(vec=4, rows=4, kchunk=2, flags=3, occupancy=0)
+    ofl.ofl_grid_tune(g.handle, ofl.ga_params(population=2, generations=1, probe_iters=2, repeats=1))
+    assert np.isfinite(_seed_time(cache, 0x19A))
+    h = ofl.Grid(synth.make_problem(45, 20, 17, seed=43), row_align=4)
+    b = ofl.ofl_batch_create([h.handle])
+    assert ofl.ofl_batch_get_tile(b).as_dict() == dict(vec=0, rows=1, kchunk=2, flags=3, occupancy=0)
+    ofl.ofl_batch_tune(b, ofl.ga_params(population=2, generations=1, probe_iters=2, repeats=1))
+    assert np.isfinite(_seed_time(cache, 0x4192))
+    ofl.ofl_batch_destroy(b)
+    g.close()
+    h.close()
