@@ -267,16 +267,21 @@ int ofl_grid_coef_bias(const ofl_grid *g, float bias[12]);
                                  HBM while j-neighbours share an L2 */
 
 typedef struct ofl_tile {
-    int vec;       /* consecutive i-points per lane: 1, 2 or 4 (a wave spans 64*vec points);
+    int vec;       /* consecutive i-points per lane: 1, 2 or 4 (a wave spans 64*vec points),
+                      or 8 (single grids marching along k, row pitch a multiple of 8
+                      elements: a wave spans two rows of 256 points, one per half-wave);
                       batches also accept 0: each grid gets the width that leaves the
-                      fewest idle lanes on its rows (one batched launch per width) */
+                      fewest idle lanes on its rows (one batched launch for all widths) */
     int rows;      /* lines per work-group = waves per work-group: 1..8 (j-rows, or k-planes
                       with OFL_TILE_MARCH_J) */
     int kchunk;    /* steps each wave marches through (k-planes, or j-rows with
                       OFL_TILE_MARCH_J): 1..1024 */
     int flags;     /* OFL_TILE_* */
-    int occupancy; /* batched launch: resident work-groups per CU (persistent kernels), 1..16;
-                      0 = one work-group per work item */
+    int occupancy; /* 0..16. Single grid: at most this many sweep work-groups resident
+                      per CU, 0 = as many as registers allow (the sweep launch reserves
+                      LDS it does not use; EINVAL from the run if the device cannot hold
+                      that reservation). Batched launch: resident work-groups per CU of
+                      persistent kernels, 0 = one work-group per work item */
 } ofl_tile;
 
 /* Set / read the sweep tile of a grid. EINVAL for values outside the ranges.
@@ -284,7 +289,8 @@ typedef struct ofl_tile {
  * vec 4, 2 or 1 for more than 128, 64 or fewer interior points per row;
  * 4 rows; 2-plane chunks; non-temporal loads; non-temporal stores for FP32
  * coefficients, and for the bfloat16 formats while OFL_FUSE_COPYBACK_SWAP is
- * set (ofl_set_fusion re-derives the default). */
+ * set (ofl_set_fusion re-derives the default); occupancy 3 for FP32
+ * coefficients at vec 4, else 0. */
 int ofl_set_tile(ofl_grid *g, const ofl_tile *tile);
 int ofl_get_tile(const ofl_grid *g, ofl_tile *tile);
 

@@ -118,11 +118,14 @@ int batch_auto_vec(int I) {
 // not start on 128-byte lines of p (a pitch that is not a multiple of 32
 // elements): one row per wave would then split lines at both ends of every
 // row load, while packed segments start on whole lines. Never for waves
-// marching along j. Measured on 64 uneven grids with 4-element alignment:
+// marching along j, nor for a grid whose coefficient rows have a pitch of
+// their own (a segment runs across row ends, so every array must share p's
+// rows and planes). Measured on 64 uneven grids with 4-element alignment:
 // FP32 76.6 -> 77.7 GLUP/s (fused 99.1 -> 99.7), bfloat16-offset 111.9 ->
 // 114.0 (fused 168.1 -> 170.3).
-bool batch_packed(int I, int J, int pitch, const TileCfg &t, int *vec, int *nseg) {
-    if (t.flags & OFL_TILE_MARCH_J)
+bool batch_packed(const Layout &L, const TileCfg &t, int *vec, int *nseg) {
+    const int I = L.I, J = L.J, pitch = L.pitch;
+    if ((t.flags & OFL_TILE_MARCH_J) || L.cpitch != pitch || L.cplane != L.plane)
         return false;
     // The packed kernels count a plane's points in 32-bit ints.
     if (static_cast<long long>(J) * pitch > 0x7fffffffLL - 4096)
@@ -200,7 +203,7 @@ void batch_build_tables(ofl_batch *b) {
         const ofl_grid *q = b->grids[static_cast<size_t>(g)];
         TileCfg t = b->tile;
         int pvec = 0, nseg = 0;
-        const bool packed = batch_packed(q->I, q->J, q->lay.pitch, b->tile, &pvec, &nseg);
+        const bool packed = batch_packed(q->lay, b->tile, &pvec, &nseg);
         t.vec = packed ? pvec : (b->tile.vec > 0 ? b->tile.vec : batch_auto_vec(q->I));
         b->gvec[static_cast<size_t>(g)] = t.vec;
         int nti, nfb, nmc;

@@ -54,7 +54,7 @@ void batch_mark_done(ofl_batch *b, int iters);
 void batch_after_run(ofl_batch *b, int iters);
 void batch_upload_views(ofl_batch *b);
 int batch_auto_vec(int I);
-bool batch_packed(int I, int J, int pitch, const ofl::TileCfg &t, int *vec, int *nseg);
+bool batch_packed(const ofl::Layout &L, const ofl::TileCfg &t, int *vec, int *nseg);
 int batch_auto_vec(int I);
 bool batch_auto_vec_tile(const ofl_tile &t);
 

@@ -44,30 +44,44 @@ Layout make_layout(int I, int J, int K, int coef_format, int row_align) {
     L.I = I;
     L.J = J;
     L.K = K;
-    // By default rows start on 128-byte boundaries for every stored element
-    // size: 32 FP32 or 64 bfloat16 elements. (A 576-byte bfloat16 row would
-    // start every other row mid-line, and a wave's 512-byte read would then
-    // touch five cache lines instead of four.) A smaller row alignment packs
-    // short rows tighter; it stays a multiple of 4 elements, so every vector
-    // load of up to 4 elements starts on its own size.
-    const int align = row_align > 0 ? row_align : (coef_format == OFL_COEF_F32 ? kPitchAlign : 2 * kPitchAlign);
-    L.pitch = round_up(I, align);
-    L.plane = static_cast<size_t>(L.pitch) * J;
-    if (row_align > 0)
-        L.plane = align_up(L.plane, static_cast<size_t>(kSegAlign));
-    L.elems = L.plane * K;
+    // By default every row starts on a 128-byte boundary: 32 elements of p and
+    // wrk2, and 32 FP32 or 64 bfloat16 elements of the coefficient arrays. (A
+    // 576-byte bfloat16 row would start every other row mid-line, and a wave's
+    // 512-byte read would then touch five cache lines instead of four.) The
+    // coefficient rows stop before i = I-1, a boundary column no nest reads, so
+    // a row of 2^n + 1 points stores 2^n coefficients and the coefficient
+    // streams run without gaps (the sweep streams gapped rows of 257 points
+    // about 2-3% slower). A smaller row alignment packs short rows tighter and
+    // keeps one layout for all arrays (packed batch rows run across row ends);
+    // it stays a multiple of 4 elements, so every vector load of up to 4
+    // elements starts on its own size.
     L.coef_elem = coef_format == OFL_COEF_F32 ? 4 : 2;
+    if (row_align > 0) {
+        L.pitch = round_up(I, row_align);
+        L.plane = align_up(static_cast<size_t>(L.pitch) * J, static_cast<size_t>(kSegAlign));
+        L.cpitch = L.pitch;
+        L.crow = I;
+        L.cplane = L.plane;
+    } else {
+        L.pitch = round_up(I, kPitchAlign);
+        L.plane = static_cast<size_t>(L.pitch) * J;
+        L.cpitch = round_up(I - 1, static_cast<int>(kPitchAlign * 4 / L.coef_elem));
+        L.crow = std::min(I, L.cpitch);
+        L.cplane = static_cast<size_t>(L.cpitch) * J;
+    }
+    L.elems = L.plane * K;
+    L.celems = L.cplane * K;
     size_t off = 0;
-    auto place = [&](size_t eb) {
+    auto place = [&](size_t n, size_t eb) {
         off = align_up(off + kGuard * eb, 256);
         const size_t at = off;
-        off += (L.elems + kGuard) * eb;
+        off += (n + kGuard) * eb;
         return at;
     };
     for (int a = 0; a < kNCoef; ++a)
-        L.off[a] = place(L.coef_elem);
-    L.off[OFL_ARR_P] = place(4);
-    L.off[OFL_ARR_WRK2] = place(4);
+        L.off[a] = place(L.celems, L.coef_elem);
+    L.off[OFL_ARR_P] = place(L.elems, 4);
+    L.off[OFL_ARR_WRK2] = place(L.elems, 4);
     L.staging_off = align_up(off, 256);
     off = L.staging_off + static_cast<size_t>(I) * J * K * 4;
     L.partials_off = align_up(off, 256);
@@ -135,7 +149,13 @@ TileCfg default_tile(int I, int fmt, unsigned fusion) {
     t.flags = OFL_TILE_NT_LOADS;
     if (fmt == OFL_COEF_F32 || (fusion & OFL_FUSE_COPYBACK_SWAP) != 0)
         t.flags |= OFL_TILE_NT_STORES;
-    t.occupancy = 0;
+    // At most 3 resident work-groups per CU (3 waves per SIMD) for the FP32
+    // sweep at 4 points per lane, whose registers would admit 4: it streams
+    // its 14 arrays faster with fewer waves. Measured at 257x257x513 on one
+    // box: 313.8-315.5 against 317.2 us per sweep (fused 314.3 against 315.9).
+    // Capping slows the other forms: bfloat16-offset 190.4 against 183.3 us
+    // there, FP32 at 2 points per lane (129x129x257) 48.9 against 46.9.
+    t.occupancy = (fmt == OFL_COEF_F32 && t.vec == 4) ? 3 : 0;
     return t;
 }
 
@@ -220,9 +240,11 @@ void grid_ensure_device(ofl_grid *g) {
     v.J = g->J;
     v.K = g->K;
     v.pitch = g->lay.pitch;
+    v.cpitch = g->lay.cpitch;
     v.nseg = 0;
     v.vec = 0;
     v.plane = static_cast<long long>(g->lay.plane);
+    v.cplane = static_cast<long long>(g->lay.cplane);
     v.partials = reinterpret_cast<double *>(g->block + g->lay.partials_off);
     v.gosa = reinterpret_cast<double *>(g->block + g->lay.gosa_off);
     g->dev_ready = true;
@@ -329,10 +351,11 @@ struct Region {
 GridView region_view(const GridView &v, const Region &r, size_t coef_bytes) {
     GridView s = v;
     const long long off = static_cast<long long>(r.k0 - 1) * v.plane + static_cast<long long>(r.j0 - 1) * v.pitch;
+    const long long coff = static_cast<long long>(r.k0 - 1) * v.cplane + static_cast<long long>(r.j0 - 1) * v.cpitch;
     s.p = v.p + off;
     s.wrk2 = v.wrk2 + off;
     for (int a = 0; a < kNCoef; ++a)
-        s.coef[a] = static_cast<const char *>(v.coef[a]) + off * static_cast<long long>(coef_bytes);
+        s.coef[a] = static_cast<const char *>(v.coef[a]) + coff * static_cast<long long>(coef_bytes);
     s.J = r.j1 - r.j0 + 2;
     s.K = r.k1 - r.k0 + 2;
     return s;
@@ -343,18 +366,22 @@ GridView region_view(const GridView &v, const Region &r, size_t coef_bytes) {
 void xfer_box(ofl_grid *g, int a, int dir, int k0, int k1, int j0, int j1) {
     const size_t eb = array_elem_bytes(g, a);
     const size_t row = static_cast<size_t>(g->I) * eb;
-    const size_t dpitch = static_cast<size_t>(g->lay.pitch) * eb;
+    const bool coef = a < kNCoef;
+    const size_t pitch = static_cast<size_t>(coef ? g->lay.cpitch : g->lay.pitch);
+    const size_t plane = coef ? g->lay.cplane : g->lay.plane;
+    const size_t width = static_cast<size_t>(coef ? g->lay.crow : g->I) * eb;  // bytes kept of each host row
     char *dev = static_cast<char *>(grid_array_ptr(g, a));
     for (int k = k0; k < k1; ++k) {
         const size_t hoff = (static_cast<size_t>(k) * g->J + j0) * row;
-        const size_t doff = (static_cast<size_t>(k) * g->lay.plane + static_cast<size_t>(j0) * g->lay.pitch) * eb;
+        const size_t doff = (static_cast<size_t>(k) * plane + static_cast<size_t>(j0) * pitch) * eb;
         if (dir == 0) {
             const char *src = static_cast<const char *>(host_src(g, a)) + hoff;
-            hip_check(hipMemcpy2DAsync(dev + doff, dpitch, src, row, row, j1 - j0, hipMemcpyHostToDevice, g->stream),
-                      "hipMemcpy2DAsync(host->device rows)");
+            hip_check(
+                hipMemcpy2DAsync(dev + doff, pitch * eb, src, row, width, j1 - j0, hipMemcpyHostToDevice, g->stream),
+                "hipMemcpy2DAsync(host->device rows)");
         } else {
             char *dst = reinterpret_cast<char *>(a == OFL_ARR_P ? g->p : g->wrk2) + hoff;
-            hip_check(hipMemcpy2DAsync(dst, row, dev + doff, dpitch, row, j1 - j0, hipMemcpyDeviceToHost, g->stream),
+            hip_check(hipMemcpy2DAsync(dst, row, dev + doff, pitch * eb, row, j1 - j0, hipMemcpyDeviceToHost, g->stream),
                       "hipMemcpy2DAsync(device->host rows)");
         }
     }
@@ -589,7 +616,8 @@ bool same_view(const GridView &a, const GridView &b) {
         if (a.coef[n] != b.coef[n] || a.bias[n] != b.bias[n])
             return false;
     return a.p == b.p && a.wrk2 == b.wrk2 && a.I == b.I && a.J == b.J && a.K == b.K && a.pitch == b.pitch &&
-           a.nseg == b.nseg && a.plane == b.plane && a.partials == b.partials && a.gosa == b.gosa;
+           a.cpitch == b.cpitch && a.nseg == b.nseg && a.plane == b.plane && a.cplane == b.cplane &&
+           a.partials == b.partials && a.gosa == b.gosa;
 }
 
 bool same_tile(const TileCfg &a, const TileCfg &b) {
@@ -858,8 +886,10 @@ void grid_exec(ofl_grid *g, const std::vector<Xfer> &xs) {
         if (x.dir == 0) {
             hip_check(hipMemcpyAsync(staging, host_src(g, x.array), bytes, hipMemcpyHostToDevice, g->stream),
                       "hipMemcpyAsync(host->device)");
-            launch_pack(staging, arr, g->I, g->J, g->K, g->lay.pitch, static_cast<long long>(g->lay.plane),
-                        static_cast<int>(eb), g->stream);
+            const bool coef = x.array < kNCoef;
+            launch_pack(staging, arr, g->I, g->J, g->K, coef ? g->lay.crow : g->I,
+                        coef ? g->lay.cpitch : g->lay.pitch,
+                        static_cast<long long>(coef ? g->lay.cplane : g->lay.plane), static_cast<int>(eb), g->stream);
             if (x.array == OFL_ARR_P || x.array == OFL_ARR_WRK2)
                 g->wrk2_boundary_ok = false;
             g->stats.h2d_count += 1;

@@ -27,7 +27,9 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <mutex>
+#include <string>
 #include <type_traits>
 #include <utility>
 #include <vector>
@@ -269,9 +271,16 @@ __device__ __forceinline__ void sweep_march(const GridView &g, int ts, int fixed
     const long long plane = g.plane;
     const float *__restrict__ p = g.p;
     auto row = [&](int j, int k) { return p + j * pitch + k * plane; };
-    // offset of the coefficients of step m, and of the step after it
+    // The coefficient arrays have rows of their own pitch, which can end
+    // before i = I-1. A lane whose vector would run past that end has no
+    // interior point, so it reads the row's last vector instead (packed rows
+    // share p's layout and stay as they are).
+    const long long cpitch = g.cpitch;
+    const long long cplane = g.cplane;
+    const int ilc = packed ? il : min(il, g.cpitch - VEC);
+    // offset of the coefficients of step m
     auto coef_off = [&](int m) {
-        return kMarchJ ? m * pitch + fixed * plane + il : fixed * pitch + m * plane + il;
+        return kMarchJ ? m * cpitch + fixed * cplane + ilc : fixed * cpitch + m * cplane + ilc;
     };
 
     // P[r][q][e]: row j-1+r, plane k-1+q, element e. EL/ER: outer neighbours.
@@ -908,11 +917,18 @@ __device__ __forceinline__ long long pitched_at(long long t, int I, int J, int p
 }
 
 template <typename T>
-__global__ void pack_kernel(const T *__restrict__ src, T *__restrict__ dst, int I, int J, long long n, int pitch,
-                            long long plane) {
+__global__ void pack_kernel(const T *__restrict__ src, T *__restrict__ dst, int I, int J, long long n, int keep,
+                            int pitch, long long plane) {
     for (long long t = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; t < n;
-         t += static_cast<long long>(gridDim.x) * blockDim.x)
-        dst[pitched_at(t, I, J, pitch, plane)] = src[t];
+         t += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const long long row = t / I;
+        const int i = static_cast<int>(t - row * I);
+        if (i < keep) {
+            const long long k = row / J;
+            const int j = static_cast<int>(row - k * J);
+            dst[k * plane + static_cast<long long>(j) * pitch + i] = src[t];
+        }
+    }
 }
 
 template <typename T>
@@ -1010,6 +1026,45 @@ using SweepLaunch = void (*)(const GridView &, const TileCfg &, float, int, int,
 using BatchSweepLaunch = void (*)(const GridView *, const SweepItem *, int, const TileCfg &, float, int, double *,
                                   const PrevParts &, hipStream_t);
 
+// Dynamic LDS per work-group that lets at most `occ` work-groups of this
+// sweep instantiation reside on a CU at once (tile.occupancy of a single
+// grid; 0: no reservation). The kernel uses none of it: the reservation only
+// bounds residency. The smallest size that does so is found through the
+// runtime's own occupancy calculator (which knows the allocation granularity
+// and the kernel's static LDS and registers), once per rows and occ; every
+// device the library runs on is a gfx950 with the same LDS per CU.
+template <int VEC, bool BF16, int FLAGS>
+size_t sweep_occupancy_lds(int rows, int occ) {
+    if (occ <= 0)
+        return 0;
+    static std::atomic<long long> memo[9][17];  // bytes + 1; 0: not yet known
+    const long long known = memo[rows][occ].load(std::memory_order_relaxed);
+    if (known > 0)
+        return static_cast<size_t>(known - 1);
+    int dev = 0, lds_cu = 0, lds_block = 0;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    hip_check(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev),
+              "hipDeviceGetAttribute(LDS per CU)");
+    hip_check(hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev),
+              "hipDeviceGetAttribute(LDS per work-group)");
+    constexpr size_t kStep = 256;
+    size_t bytes = (static_cast<size_t>(lds_cu) / static_cast<size_t>(occ + 1) / kStep + 1) * kStep;
+    for (;; bytes += kStep) {
+        if (bytes > static_cast<size_t>(lds_block))
+            fail(OFL_EINVAL, "tile.occupancy " + std::to_string(occ) +
+                                 ": the device cannot hold the LDS reservation that bounds a CU to that many "
+                                 "work-groups");
+        int resident = 0;
+        hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, sweep_kernel<VEC, BF16, FLAGS>, kWave * rows,
+                                                               bytes),
+                  "hipOccupancyMaxActiveBlocksPerMultiprocessor(sweep)");
+        if (resident <= occ)
+            break;
+    }
+    memo[rows][occ].store(static_cast<long long>(bytes) + 1, std::memory_order_relaxed);
+    return bytes;
+}
+
 template <int VEC, bool BF16, int FLAGS>
 void sweep_one(const GridView &g, const TileCfg &t, float omega, int nti, int nfb, int blocks, double *parts,
                const PrevParts &prev, hipStream_t s) {
@@ -1017,8 +1072,9 @@ void sweep_one(const GridView &g, const TileCfg &t, float omega, int nti, int nf
     const int order = (t.flags & OFL_TILE_XCD_REMAP) ? kOrderRemap
                       : ((nti * nfb) % kXcds == 0) ? kOrderBand
                                                    : kOrderPlain;
-    sweep_kernel<VEC, BF16, FLAGS><<<blocks, kWave * t.rows, 0, s>>>(g, t.kchunk, nti, nfb, omega, order, parts,
-                                                                       prev);
+    const size_t lds = sweep_occupancy_lds<VEC, BF16, FLAGS>(t.rows, t.occupancy);
+    sweep_kernel<VEC, BF16, FLAGS><<<blocks, kWave * t.rows, lds, s>>>(g, t.kchunk, nti, nfb, omega, order, parts,
+                                                                         prev);
 }
 
 template <int VEC, bool BF16, int FLAGS>
@@ -1269,16 +1325,16 @@ void launch_batch_copyback(const GridView *views, const RowItem *items, int nite
     check_launch("batched copy-back kernel launch");
 }
 
-void launch_pack(const void *staging, void *arr, int I, int J, int K, int pitch, long long plane, int elem_bytes,
-                 hipStream_t s) {
+void launch_pack(const void *staging, void *arr, int I, int J, int K, int keep, int pitch, long long plane,
+                 int elem_bytes, hipStream_t s) {
     const long long n = static_cast<long long>(J) * K * I;
     const int blocks = grid_for(n, 256, 65536);
     if (elem_bytes == 4)
         pack_kernel<float><<<blocks, 256, 0, s>>>(static_cast<const float *>(staging), static_cast<float *>(arr), I, J,
-                                                 n, pitch, plane);
+                                                 n, keep, pitch, plane);
     else
         pack_kernel<uint16_t><<<blocks, 256, 0, s>>>(static_cast<const uint16_t *>(staging),
-                                                    static_cast<uint16_t *>(arr), I, J, n, pitch, plane);
+                                                    static_cast<uint16_t *>(arr), I, J, n, keep, pitch, plane);
     check_launch("pack kernel launch");
 }
 

@@ -46,9 +46,14 @@ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 // last interior point stay inside the allocation.
 struct Layout {
     int I = 0, J = 0, K = 0;
-    int pitch = 0;          // elements per row
+    int pitch = 0;          // elements per row of p and wrk2
     size_t plane = 0;       // elements per plane: pitch * J (compact rows: padded to kSegAlign)
-    size_t elems = 0;       // pitch * J * K
+    size_t elems = 0;       // plane * K
+    // The twelve coefficient arrays: rows of cpitch elements holding i = 0 ..
+    // crow-1 (the default layout leaves out i = I-1, a boundary column that no
+    // nest reads), planes of cplane, celems in all. Compact rows: as p.
+    int cpitch = 0, crow = 0;
+    size_t cplane = 0, celems = 0;
     size_t coef_elem = 4;   // bytes per stored coefficient (4 or 2)
     size_t off[OFL_NARRAYS] = {};  // byte offset of element 0 of each array in the block
     size_t staging_off = 0; // contiguous I*J*K*4-byte staging buffer for transfers
@@ -66,6 +71,7 @@ struct GridView {
     const void *coef[kNCoef];  // float* (FP32) or uint16_t* (bfloat16 formats)
     float bias[kNCoef];
     int I, J, K, pitch;
+    int cpitch;  // row pitch of the coefficient arrays (elements)
     // Batched grids only: > 0 when the grid runs in packed rows, as this many
     // segments of 64 * VEC consecutive points per plane (rows 1..J-2), each
     // wave's line running across row ends; 0 for the row-per-wave form.
@@ -74,6 +80,7 @@ struct GridView {
     // whose items mix vector widths; unused elsewhere.
     int vec;
     long long plane;
+    long long cplane;  // plane stride of the coefficient arrays (elements)
     double *partials;  // residual partial sums (batched: base of this grid's range)
     double *gosa;      // device scalar
 };
@@ -145,8 +152,10 @@ void launch_residual(const GridView &g, int vec, int sum_mode, int flags, float 
 // (launch_residual(..., false)); the copy-back's block 0 does it first.
 void launch_copyback(const GridView &g, int vec, int flags, hipStream_t s, bool whole_rows = false,
                      bool finalize_residual = false, float omega = 1.f);
-void launch_pack(const void *staging, void *arr, int I, int J, int K, int pitch, long long plane, int elem_bytes,
-                 hipStream_t s);
+// Host-order staging (rows of I elements) into a pitched device array that
+// keeps the first `keep` elements of every row (keep <= I, keep <= pitch).
+void launch_pack(const void *staging, void *arr, int I, int J, int K, int keep, int pitch, long long plane,
+                 int elem_bytes, hipStream_t s);
 void launch_unpack(const void *arr, void *staging, int I, int J, int K, int pitch, long long plane, int elem_bytes,
                    hipStream_t s);
 void launch_fill_zero(void *ptr, size_t bytes, hipStream_t s);

@@ -16,7 +16,9 @@
 //                       MI355X: more work-groups keep more loads in flight)
 //   bits 7-11 flags     OFL_TILE_NT_LOADS | OFL_TILE_NT_STORES | OFL_TILE_PREFETCH |
 //                       OFL_TILE_MARCH_J | OFL_TILE_XCD_REMAP
-//   bits 12-13 (batch)  occupancy 0 (one work-group per item), 2, 4, 8 per CU
+//   bits 12-13          occupancy: single grids 0 (no cap), 2, 3, 4 resident
+//                       sweep work-groups per CU; batches 0 (one work-group per
+//                       item), 2, 4, 8 persistent work-groups per CU
 //   bit 14 (batch)      vector width chosen per grid (overrides bits 0-1)
 #include <algorithm>
 #include <chrono>
@@ -54,7 +56,7 @@ struct Rng {
     double uniform() { return static_cast<double>(next() >> 11) * 0x1.0p-53; }
 };
 
-int gene_bits(bool batch) { return batch ? 15 : 12; }
+int gene_bits(bool batch) { return batch ? 15 : 14; }
 
 bool decode(uint32_t gene, bool batch, TileCfg *t) {
     const int v = static_cast<int>(gene & 3u);
@@ -65,7 +67,7 @@ bool decode(uint32_t gene, bool batch, TileCfg *t) {
     t->kchunk = 1 << ((gene >> 4) & 7u);
     t->flags = static_cast<int>((gene >> 7) & 31u);
     const int occ = static_cast<int>((gene >> 12) & 3u);
-    t->occupancy = batch ? (occ == 0 ? 0 : (1 << occ)) : 0;
+    t->occupancy = occ == 0 ? 0 : (batch ? (1 << occ) : occ + 1);
     if (batch && ((gene >> 14) & 1u))
         t->vec = 0;
     return true;
@@ -91,6 +93,8 @@ uint32_t encode(const TileCfg &t, bool batch) {
         while (o < 3 && (1 << o) < t.occupancy)
             ++o;
         g |= static_cast<uint32_t>(t.occupancy == 0 ? 0 : o) << 12;
+    } else if (t.occupancy > 0) {
+        g |= static_cast<uint32_t>(std::min(std::max(t.occupancy, 2), 4) - 1) << 12;
     }
     return g;
 }

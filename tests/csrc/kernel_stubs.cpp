@@ -14,7 +14,7 @@ void launch_sweep(const GridView &, const TileCfg &, int, float, hipStream_t, do
 void launch_finalize(const double *, long long, float, double *, hipStream_t, double *, int) { no_device(); }
 void launch_residual(const GridView &, int, int, int, float, hipStream_t, bool) { no_device(); }
 void launch_copyback(const GridView &, int, int, hipStream_t, bool, bool, float) { no_device(); }
-void launch_pack(const void *, void *, int, int, int, int, long long, int, hipStream_t) { no_device(); }
+void launch_pack(const void *, void *, int, int, int, int, int, long long, int, hipStream_t) { no_device(); }
 void launch_unpack(const void *, void *, int, int, int, int, long long, int, hipStream_t) { no_device(); }
 void launch_fill_zero(void *, size_t, hipStream_t) { no_device(); }
 void launch_copy(void *, const void *, size_t, hipStream_t) { no_device(); }

@@ -1,5 +1,8 @@
 """Seeded random grids x random tiles x random fusion on the GPU.
 
+A tile's occupancy caps the sweep's resident work-groups per CU by an LDS
+reservation the kernel never touches, so it changes only timing.
+
 Every point of the sweep is computed by the same fused multiply-adds in the
 same order at every tile, vector width and fusion setting, so p must be
 bitwise equal to the run with the default tile, and the residual equal up to
@@ -46,6 +49,8 @@ def case(seed):
     fusion = int(rng.choice([0, ofl.OFL_FUSE_RESIDUAL, ofl.OFL_FUSE_COPYBACK_SWAP,
                              ofl.OFL_FUSE_RESIDUAL | ofl.OFL_FUSE_COPYBACK_SWAP]))
     iters = int(rng.integers(1, 6))
+    # drawn last, so the cases above keep their earlier draws
+    tile["occupancy"] = int(rng.choice([0, 0, 1, 2, 3, 4, 8, 16]))
     return (I, J, K), fmt, tile, fusion, iters
 
 
@@ -85,3 +90,18 @@ def test_random_tile_equals_default_tile_and_oracle(seed):
     if go != 0.0:
         assert rel_err(gosa, go) <= TOL_GOSA_F32
     assert boundary_equal(p, a["p"])
+
+
+@pytest.mark.parametrize("fmt", [ofl.OFL_COEF_F32, ofl.OFL_COEF_BF16_OFFSET])
+def test_occupancy_caps_leave_results_bitwise_unchanged(fmt):
+    """Every cap from one work-group per CU (half of a CU's LDS reserved per
+    work-group) to 16, plain and fused: p and the residual (summed in a fixed
+    order either way) bitwise equal to the uncapped run."""
+    a = synth.make_problem(300, 40, 30, seed=77)
+    base = dict(vec=4, rows=4, kchunk=2, flags=ofl.OFL_TILE_NT_LOADS | ofl.OFL_TILE_NT_STORES)
+    for fusion in (0, ofl.OFL_FUSE_RESIDUAL | ofl.OFL_FUSE_COPYBACK_SWAP):
+        p0, g0 = run(a, fmt, 4, dict(base, occupancy=0), fusion)
+        for occ in (1, 2, 3, 4, 5, 8, 16):
+            say("occupancy", occ, "fmt", fmt, "fusion", fusion)
+            p, g = run(a, fmt, 4, dict(base, occupancy=occ), fusion)
+            assert np.array_equal(p, p0) and g == g0, occ

@@ -88,15 +88,29 @@ def test_device_bytes_follow_the_row_alignment():
     assert ofl.ofl_grid_device_bytes(96, 33, 65, ofl.OFL_COEF_F32, 0) == 12_488_704
     assert ofl.ofl_grid_device_bytes(32, 33, 65, ofl.OFL_COEF_F32, 32) == 4_366_336
     assert ofl.ofl_grid_device_bytes(32, 33, 65, ofl.OFL_COEF_F32, 0) == 4_251_648
-    # a lower bound from the layout's rules, for every alignment and format
-    for I, J, K in [(3, 3, 3), (33, 33, 65), (97, 41, 12), (161, 7, 9)]:
+    # a lower bound from the layout's rules, for every alignment and format:
+    # compact rows share one pitch; 128-byte rows give the coefficient arrays
+    # rows that end before the boundary column i = I-1
+    def up(x, a):
+        return -(-x // a) * a
+
+    for I, J, K in [(3, 3, 3), (33, 33, 65), (97, 41, 12), (161, 7, 9), (257, 5, 4)]:
         for fmt, eb in ((ofl.OFL_COEF_F32, 4), (ofl.OFL_COEF_BF16_OFFSET, 2)):
             for ra in (0, 4, 8, 16, 32):
-                align = ra or (32 if fmt == ofl.OFL_COEF_F32 else 64)
-                pitch = -(-I // align) * align
-                plane = pitch * J if ra == 0 else -(-(pitch * J) // 64) * 64
-                need = 12 * (plane * K + 2 * 1024) * eb + 2 * (plane * K + 2 * 1024) * 4 + I * J * K * 4
+                if ra:
+                    plane = cplane = up(up(I, ra) * J, 64)
+                else:
+                    plane, cplane = up(I, 32) * J, up(I - 1, 128 // eb) * J
+                need = 12 * (cplane * K + 2 * 1024) * eb + 2 * (plane * K + 2 * 1024) * 4 + I * J * K * 4
                 assert ofl.ofl_grid_device_bytes(I, J, K, fmt, ra) >= need, (I, J, K, fmt, ra)
+    # 257 points per row: 256-element coefficient rows, 288-element rows of p
+    # and wrk2 (one layout for all arrays took 288 FP32 or 320 bfloat16
+    # elements per row), each array with 1024 elements of guard on each side,
+    # plus the staging buffer, partials and alignment
+    for fmt, eb in ((ofl.OFL_COEF_F32, 4), (ofl.OFL_COEF_BF16_OFFSET, 2)):
+        arrays = 12 * (256 * 257 * 513 + 2048) * eb + 2 * (288 * 257 * 513 + 2048) * 4
+        extra = ofl.ofl_grid_device_bytes(257, 257, 513, fmt, 0) - arrays - 257 * 257 * 513 * 4
+        assert 8 * 2048 <= extra < 8 * 2048 + 16 * 4096, (fmt, extra)
     for bad in (1, 3, 64, -4):
         with pytest.raises(ofl.OflError) as e:
             ofl.ofl_grid_device_bytes(33, 33, 65, ofl.OFL_COEF_F32, bad)
@@ -158,8 +172,9 @@ def test_run_validates_arguments():
 def test_default_tile_follows_row_length_format_and_fusion():
     """A new grid's sweep tile: the vector width from the row length, 2-plane
     chunks, non-temporal loads, and non-temporal stores for FP32 coefficients
-    or, for the bfloat16 formats, while the copy-back is a buffer exchange.
-    A tile the caller sets stays, whatever the fusion."""
+    or, for the bfloat16 formats, while the copy-back is a buffer exchange; at
+    most 3 resident work-groups per CU for FP32 at 4 points per lane. A tile
+    the caller sets stays, whatever the fusion."""
     nt, ns = ofl.OFL_TILE_NT_LOADS, ofl.OFL_TILE_NT_STORES
     f32, bf = ofl.OFL_COEF_F32, ofl.OFL_COEF_BF16_OFFSET
     swap = ofl.OFL_FUSE_COPYBACK_SWAP
@@ -169,7 +184,7 @@ def test_default_tile_follows_row_length_format_and_fusion():
                                        (300, f32, swap, 4, nt | ns)]:
         g = ofl.Grid(synth.make_problem(I, 5, 4), coef_format=fmt)
         ofl.ofl_set_fusion(g.handle, fusion)
-        want = dict(vec=vec, rows=4, kchunk=2, flags=flags, occupancy=0)
+        want = dict(vec=vec, rows=4, kchunk=2, flags=flags, occupancy=3 if (fmt == f32 and vec == 4) else 0)
         assert ofl.ofl_get_tile(g.handle).as_dict() == want, (I, fmt, fusion)
         ofl.ofl_set_fusion(g.handle, 0)
         assert ofl.ofl_get_tile(g.handle).flags == (nt | ns if fmt == f32 else nt)
