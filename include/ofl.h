@@ -289,8 +289,9 @@ typedef struct ofl_tile {
  * vec 4, 2 or 1 for more than 128, 64 or fewer interior points per row;
  * 4 rows; 2-plane chunks; non-temporal loads; non-temporal stores for FP32
  * coefficients, and for the bfloat16 formats while OFL_FUSE_COPYBACK_SWAP is
- * set (ofl_set_fusion re-derives the default); occupancy 3 for FP32
- * coefficients at vec 4, else 0. */
+ * set (ofl_set_fusion re-derives the default); for FP32 coefficients at
+ * vec 4, occupancy 3 and, unless OFL_FUSE_RESIDUAL is set,
+ * OFL_TILE_PREFETCH; else occupancy 0. */
 int ofl_set_tile(ofl_grid *g, const ofl_tile *tile);
 int ofl_get_tile(const ofl_grid *g, ofl_tile *tile);
 

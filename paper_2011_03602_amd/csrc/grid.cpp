@@ -149,13 +149,22 @@ TileCfg default_tile(int I, int fmt, unsigned fusion) {
     t.flags = OFL_TILE_NT_LOADS;
     if (fmt == OFL_COEF_F32 || (fusion & OFL_FUSE_COPYBACK_SWAP) != 0)
         t.flags |= OFL_TILE_NT_STORES;
-    // At most 3 resident work-groups per CU (3 waves per SIMD) for the FP32
-    // sweep at 4 points per lane, whose registers would admit 4: it streams
-    // its 14 arrays faster with fewer waves. Measured at 257x257x513 on one
-    // box: 313.8-315.5 against 317.2 us per sweep (fused 314.3 against 315.9).
-    // Capping slows the other forms: bfloat16-offset 190.4 against 183.3 us
-    // there, FP32 at 2 points per lane (129x129x257) 48.9 against 46.9.
-    t.occupancy = (fmt == OFL_COEF_F32 && t.vec == 4) ? 3 : 0;
+    // The FP32 sweep at 4 points per lane streams its 14 arrays fastest with
+    // 3 waves per SIMD, though its registers would admit 4: at most 3 resident
+    // work-groups per CU. Unless the residual is fused into it, it also loads
+    // each step's coefficients one step ahead (its registers then admit only
+    // 3 waves anyway). Measured at 257x257x513 on one box, us per sweep: 317.2
+    // uncapped, 313.8-314.0 capped, 310.1-311.3 capped with the early loads;
+    // fused 316.6-316.9, 314.0 capped, 331.1 with the early loads. Capping
+    // slows the other forms: bfloat16-offset 190.4 against 183.3 us there,
+    // FP32 at 2 points per lane (129x129x257) 48.8 against 46.8.
+    if (fmt == OFL_COEF_F32 && t.vec == 4) {
+        t.occupancy = 3;
+        if ((fusion & OFL_FUSE_RESIDUAL) == 0)
+            t.flags |= OFL_TILE_PREFETCH;
+    } else {
+        t.occupancy = 0;
+    }
     return t;
 }
 

@@ -115,13 +115,14 @@ def test_searches_measure_the_tile_they_start_from(cache):
     """The population starts with the current tile's gene: it must decode back
     to a buildable tile and be measured (a finite time in the file). The default
     FP32 grid tile (4 points per lane, 4 rows, 2-plane chunks, NT loads and
-    stores, at most 3 work-groups per CU) is gene 0x219a; the default batch
+    stores, early coefficient loads, at most 3 work-groups per CU) is gene
+    0x239a; the default batch
     tile (each grid's own width, 1 row, 2-plane chunks, NT loads and stores,
     bit 14 set) is gene 0x4192."""
     g = ofl.Grid(synth.make_problem(200, 21, 19, seed=42))
-    assert ofl.ofl_get_tile(g.handle).as_dict() == dict(vec=4, rows=4, kchunk=2, flags=3, occupancy=3)
+    assert ofl.ofl_get_tile(g.handle).as_dict() == dict(vec=4, rows=4, kchunk=2, flags=7, occupancy=3)
     ofl.ofl_grid_tune(g.handle, ofl.ga_params(population=2, generations=1, probe_iters=2, repeats=1))
-    assert np.isfinite(_seed_time(cache, 0x219A))
+    assert np.isfinite(_seed_time(cache, 0x239A))
     h = ofl.Grid(synth.make_problem(45, 20, 17, seed=43), row_align=4)
     b = ofl.ofl_batch_create([h.handle])
     assert ofl.ofl_batch_get_tile(b).as_dict() == dict(vec=0, rows=1, kchunk=2, flags=3, occupancy=0)

@@ -172,22 +172,27 @@ def test_run_validates_arguments():
 def test_default_tile_follows_row_length_format_and_fusion():
     """A new grid's sweep tile: the vector width from the row length, 2-plane
     chunks, non-temporal loads, and non-temporal stores for FP32 coefficients
-    or, for the bfloat16 formats, while the copy-back is a buffer exchange; at
-    most 3 resident work-groups per CU for FP32 at 4 points per lane. A tile
-    the caller sets stays, whatever the fusion."""
+    or, for the bfloat16 formats, while the copy-back is a buffer exchange; for
+    FP32 at 4 points per lane, at most 3 resident work-groups per CU and, unless
+    the residual is fused, coefficients loaded a step ahead. A tile the caller
+    sets stays, whatever the fusion."""
     nt, ns = ofl.OFL_TILE_NT_LOADS, ofl.OFL_TILE_NT_STORES
     f32, bf = ofl.OFL_COEF_F32, ofl.OFL_COEF_BF16_OFFSET
     swap = ofl.OFL_FUSE_COPYBACK_SWAP
     for I, fmt, fusion, vec, flags in [(300, f32, 0, 4, nt | ns), (100, f32, 0, 2, nt | ns), (40, f32, 0, 1, nt | ns),
                                        (300, bf, 0, 4, nt), (40, ofl.OFL_COEF_BF16, 0, 1, nt),
                                        (300, bf, swap, 4, nt | ns), (300, bf, ofl.OFL_FUSE_RESIDUAL, 4, nt),
-                                       (300, f32, swap, 4, nt | ns)]:
+                                       (300, f32, swap, 4, nt | ns), (300, f32, ofl.OFL_FUSE_RESIDUAL, 4, nt | ns)]:
         g = ofl.Grid(synth.make_problem(I, 5, 4), coef_format=fmt)
         ofl.ofl_set_fusion(g.handle, fusion)
-        want = dict(vec=vec, rows=4, kchunk=2, flags=flags, occupancy=3 if (fmt == f32 and vec == 4) else 0)
+        f32v4 = fmt == f32 and vec == 4
+        if f32v4 and not fusion & ofl.OFL_FUSE_RESIDUAL:
+            flags |= ofl.OFL_TILE_PREFETCH
+        want = dict(vec=vec, rows=4, kchunk=2, flags=flags, occupancy=3 if f32v4 else 0)
         assert ofl.ofl_get_tile(g.handle).as_dict() == want, (I, fmt, fusion)
         ofl.ofl_set_fusion(g.handle, 0)
-        assert ofl.ofl_get_tile(g.handle).flags == (nt | ns if fmt == f32 else nt)
+        pf = ofl.OFL_TILE_PREFETCH if f32v4 else 0
+        assert ofl.ofl_get_tile(g.handle).flags == (nt | ns | pf if fmt == f32 else nt)
         g.close()
     g = ofl.Grid(synth.make_problem(300, 5, 4), coef_format=bf)
     mine = ofl.tile(vec=2, rows=3, kchunk=5, flags=nt)
