@@ -383,7 +383,9 @@ typedef struct ofl_batch ofl_batch;
  * ownership of their arrays; the batch borrows them and must be destroyed
  * first. tile may be NULL: the vector width per grid (vec 0), 1 line per
  * work-group, 2-plane chunks for FP32 coefficients and 4-plane ones for the
- * bfloat16 formats, non-temporal loads and stores. Unless the tile
+ * bfloat16 formats, non-temporal loads and stores; unfused bfloat16 batches
+ * take vec 4 and 2 lines per work-group instead (ofl_batch_set_fusion
+ * re-derives the default until a tile is set or searched). Unless the tile
  * has OFL_TILE_XCD_REMAP, each grid's sweep items are ordered so that every
  * XCD receives runs of consecutive lines (which share halo rows). A grid created
  * with a compact desc.row_align whose rows fill few of a wave's lanes runs in

@@ -123,6 +123,35 @@ int batch_auto_vec(int I) {
 // rows and planes). Measured on 64 uneven grids with 4-element alignment:
 // FP32 76.6 -> 77.7 GLUP/s (fused 99.1 -> 99.7), bfloat16-offset 111.9 ->
 // 114.0 (fused 168.1 -> 170.3).
+TileCfg batch_default_tile(int fmt, unsigned fusion) {
+    TileCfg t;
+    t.vec = 0;
+    // One row per work-group: with the XCD bands of the item list it beat 4
+    // rows in all four forms (FP32 73.8 against 73.2 GLUP/s, fused 94.0
+    // against 93.2; bfloat16-offset 110.1 against 109.7, fused 163.3 against
+    // 163.0).
+    t.rows = 1;
+    // 2-plane chunks for FP32 coefficients (77.8 against 76.1 GLUP/s, fused
+    // 97.3 against 96.1), 4 for bfloat16 ones (113.3 against 112.3, fused
+    // 166.0 against 160.2).
+    t.kchunk = fmt == OFL_COEF_F32 ? 2 : 4;
+    // Non-temporal stores as well: measured on 64 uneven grids they add 6% to
+    // the plain batch and 7-18% to the fused one. (Ordinary stores in the
+    // copy-back alone make it 1.6x faster, but the next sweep then writes the
+    // dirty lines of p back and loses as much.)
+    t.flags = OFL_TILE_NT_LOADS | OFL_TILE_NT_STORES;
+    t.occupancy = 0;
+    // The unfused bfloat16 batch: 4 points per lane in every grid and 2 rows
+    // per work-group, the batch GA's pick, 114.5-114.6 against 113.5-113.6
+    // GLUP/s on 64 uneven grids (fused, the GA's pick is within noise of the
+    // tile above).
+    if (fmt != OFL_COEF_F32 && fusion == 0) {
+        t.vec = 4;
+        t.rows = 2;
+    }
+    return t;
+}
+
 bool batch_packed(const Layout &L, const TileCfg &t, int *vec, int *nseg) {
     const int I = L.I, J = L.J, pitch = L.pitch;
     if ((t.flags & OFL_TILE_MARCH_J) || L.cpitch != pitch || L.cplane != L.plane)
@@ -474,23 +503,9 @@ int ofl_batch_create(ofl_grid *const *grids, int n, const ofl_tile *tile, ofl_ba
         b->sum_mode = grids[0]->sum_mode;
         if (tile) {
             b->tile = to_cfg(*tile);
+            b->tile_chosen = true;
         } else {
-            b->tile.vec = 0;
-            // One row per work-group: with the XCD bands of the item list it
-            // beat 4 rows in all four forms (FP32 73.8 against 73.2 GLUP/s,
-            // fused 94.0 against 93.2; bfloat16-offset 110.1 against 109.7,
-            // fused 163.3 against 163.0).
-            b->tile.rows = 1;
-            // 2-plane chunks for FP32 coefficients (77.8 against 76.1 GLUP/s,
-            // fused 97.3 against 96.1), 4 for bfloat16 ones (113.3 against
-            // 112.3, fused 166.0 against 160.2).
-            b->tile.kchunk = b->fmt == OFL_COEF_F32 ? 2 : 4;
-            // Non-temporal stores as well: measured on 64 uneven grids they add 6%
-            // to the plain batch and 7-18% to the fused one. (Ordinary stores in
-            // the copy-back alone make it 1.6x faster, but the next sweep then
-            // writes the dirty lines of p back and loses as much.)
-            b->tile.flags = OFL_TILE_NT_LOADS | OFL_TILE_NT_STORES;
-            b->tile.occupancy = 0;
+            b->tile = batch_default_tile(b->fmt, 0);
         }
         for (ofl_grid *g : b->grids)
             grid_ensure_device(g);
@@ -534,6 +549,7 @@ int ofl_batch_set_tile(ofl_batch *b, const ofl_tile *tile) {
             free_tables(b);
             b->tile = c;
         }
+        b->tile_chosen = true;
     });
 }
 
@@ -550,6 +566,14 @@ int ofl_batch_set_fusion(ofl_batch *b, unsigned flags) {
             hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
             drop_graph(b);
             b->fusion = flags;
+            if (!b->tile_chosen) {
+                const TileCfg t = batch_default_tile(b->fmt, flags);
+                if (t.vec != b->tile.vec || t.rows != b->tile.rows || t.kchunk != b->tile.kchunk ||
+                    t.flags != b->tile.flags || t.occupancy != b->tile.occupancy) {
+                    free_tables(b);
+                    b->tile = t;
+                }
+            }
         }
     });
 }

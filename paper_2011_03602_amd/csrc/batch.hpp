@@ -14,6 +14,7 @@ struct ofl_batch {
     int cu_count = 256;
     hipStream_t stream = nullptr;
     ofl::TileCfg tile;
+    bool tile_chosen = false;  // set by the caller or a search: fusion leaves it as it is
 
     unsigned fusion = 0;  // OFL_FUSE_* bits for the batched iterations
 
@@ -55,6 +56,9 @@ void batch_after_run(ofl_batch *b, int iters);
 void batch_upload_views(ofl_batch *b);
 int batch_auto_vec(int I);
 bool batch_packed(const ofl::Layout &L, const ofl::TileCfg &t, int *vec, int *nseg);
+// A new batch's tile for coefficient format fmt and fusion bits, re-derived by
+// ofl_batch_set_fusion until a tile is set or searched.
+ofl::TileCfg batch_default_tile(int fmt, unsigned fusion);
 int batch_auto_vec(int I);
 bool batch_auto_vec_tile(const ofl_tile &t);
 

@@ -603,6 +603,39 @@ def test_batch_per_grid_vector_width(fmt):
         g.close()
 
 
+def test_batch_default_tile_follows_format_and_fusion():
+    """A batch without a tile of its own: each grid's width, one line per
+    work-group, 2-plane chunks (FP32) or 4-plane ones (bfloat16), non-temporal
+    loads and stores; unfused bfloat16 batches 4 points per lane and 2 lines.
+    Fusion re-derives it until a tile is set; the unfused bfloat16 default is
+    checked against the FP64 oracle at the bfloat16 bar."""
+    say("batch default tiles")
+    probs = _small_batch(3)
+    fuse = ofl.OFL_FUSE_RESIDUAL | ofl.OFL_FUSE_COPYBACK_SWAP
+    for fmt in (ofl.OFL_COEF_F32, ofl.OFL_COEF_BF16_OFFSET):
+        f32 = fmt == ofl.OFL_COEF_F32
+        fused = dict(vec=0, rows=1, kchunk=2 if f32 else 4, flags=3, occupancy=0)
+        plain = fused if f32 else dict(fused, vec=4, rows=2)
+        grids = [ofl.Grid(a, coef_format=fmt) for a in probs]
+        b = ofl.ofl_batch_create([g.handle for g in grids])
+        assert ofl.ofl_batch_get_tile(b).as_dict() == plain
+        if not f32:
+            gosa = ofl.ofl_batch_run(b, 4, OMEGA, len(grids))
+            for a, g, r in zip(probs, grids, gosa):
+                check_against_oracle(a, g, r, 4, tol_p=TOL_BF16, tol_g=TOL_BF16)
+        ofl.ofl_batch_set_fusion(b, fuse)
+        assert ofl.ofl_batch_get_tile(b).as_dict() == fused
+        ofl.ofl_batch_set_fusion(b, 0)
+        assert ofl.ofl_batch_get_tile(b).as_dict() == plain
+        mine = ofl.tile(vec=2, rows=3, kchunk=5, flags=1)
+        ofl.ofl_batch_set_tile(b, mine)
+        ofl.ofl_batch_set_fusion(b, fuse)
+        assert ofl.ofl_batch_get_tile(b).as_dict() == mine.as_dict()
+        ofl.ofl_batch_destroy(b)
+        for g in grids:
+            g.close()
+
+
 @pytest.mark.parametrize("fusion", [ofl.OFL_FUSE_RESIDUAL, ofl.OFL_FUSE_COPYBACK_SWAP,
                                     ofl.OFL_FUSE_RESIDUAL | ofl.OFL_FUSE_COPYBACK_SWAP])
 @pytest.mark.parametrize("fmt", [ofl.OFL_COEF_F32, ofl.OFL_COEF_BF16_OFFSET])
