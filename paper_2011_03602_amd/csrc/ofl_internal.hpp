@@ -20,7 +20,8 @@ constexpr int kPitchAlign = 32;   // FP32 elements per 128 bytes (row alignment 
 constexpr size_t kGuard = 1024;   // elements of slack before and after every device array
 constexpr int kResidualBlocks = 2048;  // fixed -> deterministic residual partials
 constexpr int kResidualThreads = 256;
-constexpr int kRowUnroll = 4;
+constexpr int kRowUnroll = 4;   // row tiles a residual wave keeps in flight
+constexpr int kCopyUnroll = 16;  // row tiles a copy-back wave keeps in flight
 // Template flags of the sweep kernels are the low four OFL_TILE_* bits (the
 // XCD order is a launch argument, not a template flag) plus this internal bit,
 // which sits where the public tile flags keep OFL_TILE_XCD_REMAP: the sweep
