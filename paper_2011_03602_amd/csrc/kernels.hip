@@ -830,24 +830,26 @@ __global__ __launch_bounds__(512) void batch_fold_finalize_kernel(const GridView
 // and row padding), so every interior row is copied whole, boundary columns and
 // padding included. The result is the same, and every 128-byte line of those
 // rows is written in full instead of in part.
-template <int VEC, bool NTL, bool NTS>
+// U row tiles per round: every load of a round is in flight before its first
+// store.
+template <int VEC, bool NTL, bool NTS, int U>
 __device__ __forceinline__ void copyback_rows(const GridView &g, int first, int count, bool whole_rows) {
     const int lane = threadIdx.x & (kWave - 1);
     const int nti = itiles(g.I, VEC);
     const int I = g.I;
     const int last = first + count - 1;
-    for (int r0 = first; r0 <= last; r0 += kCopyUnroll) {
-        float wv[kCopyUnroll][VEC];
-        long long off[kCopyUnroll];
-        int ib[kCopyUnroll];
-        bool ok[kCopyUnroll];
+    for (int r0 = first; r0 <= last; r0 += U) {
+        float wv[U][VEC];
+        long long off[U];
+        int ib[U];
+        bool ok[U];
 #pragma unroll
-        for (int u = 0; u < kCopyUnroll; ++u) {
+        for (int u = 0; u < U; ++u) {
             off[u] = row_tile_offset<VEC>(g, min(r0 + u, last), nti, lane, ib[u], ok[u], whole_rows);
             load_f32<VEC, NTL>(g.wrk2 + off[u], wv[u]);
         }
 #pragma unroll
-        for (int u = 0; u < kCopyUnroll; ++u) {
+        for (int u = 0; u < U; ++u) {
             if (r0 + u > last)
                 continue;
             if (whole_rows) {
@@ -868,7 +870,7 @@ __device__ __forceinline__ void copyback_rows(const GridView &g, int first, int 
 // fin_n > 0: the residual nest ran just before as its own kernel and left
 // fin_n block partials; block 0 first turns them into gosa (the finalize step,
 // with the same fixed order), so that step needs no launch of its own.
-template <int VEC, bool NTL, bool NTS>
+template <int VEC, bool NTL, bool NTS, int U>
 __global__ __launch_bounds__(kResidualThreads) void copyback_kernel(GridView g, int rows_per_wave, int nrt,
                                                                     int whole_rows, int fin_n, double omega) {
     if (fin_n > 0 && blockIdx.x == 0)
@@ -876,7 +878,7 @@ __global__ __launch_bounds__(kResidualThreads) void copyback_kernel(GridView g, 
     const int wave = blockIdx.x * (kResidualThreads / kWave) + static_cast<int>(threadIdx.x / kWave);
     const int first = wave * rows_per_wave;
     const int count = max(0, min(rows_per_wave, nrt - first));
-    copyback_rows<VEC, NTL, NTS>(g, first, count, whole_rows != 0);
+    copyback_rows<VEC, NTL, NTS, U>(g, first, count, whole_rows != 0);
 }
 
 template <int VEC, bool NTL, bool NTS>
@@ -893,13 +895,13 @@ __global__ __launch_bounds__(kResidualThreads) void batch_copyback_kernel(const 
         const int count = max(0, min(per, item.first + item.count - first));
         if constexpr (VEC == 0) {
             if (g.vec == 1)
-                copyback_rows<1, NTL, NTS>(g, first, count, whole_rows != 0);
+                copyback_rows<1, NTL, NTS, kCopyUnroll>(g, first, count, whole_rows != 0);
             else if (g.vec == 2)
-                copyback_rows<2, NTL, NTS>(g, first, count, whole_rows != 0);
+                copyback_rows<2, NTL, NTS, kCopyUnroll>(g, first, count, whole_rows != 0);
             else
-                copyback_rows<4, NTL, NTS>(g, first, count, whole_rows != 0);
+                copyback_rows<4, NTL, NTS, kCopyUnroll>(g, first, count, whole_rows != 0);
         } else {
-            copyback_rows<VEC, NTL, NTS>(g, first, count, whole_rows != 0);
+            copyback_rows<VEC, NTL, NTS, kCopyUnroll>(g, first, count, whole_rows != 0);
         }
     }
 }
@@ -1256,11 +1258,15 @@ struct BatchResidualLaunch {
 template <int VEC, int NTS, bool NTL>
 struct CopybackLaunch {
     static void run(dim3 grid, dim3 block, hipStream_t s, const GridView &g, int rpw, int nrt, int whole_rows,
-                    int fin_n, double omega) {
+                    int fin_n, double omega, bool wide) {
         if constexpr (VEC == 0)
             fail(OFL_EINVAL, "a single grid's copy-back runs 1, 2 or 4 points per lane");
+        else if (wide)
+            copyback_kernel<VEC, NTL, NTS != 0, kCopyUnroll>
+                <<<grid, block, 0, s>>>(g, rpw, nrt, whole_rows, fin_n, omega);
         else
-            copyback_kernel<VEC, NTL, NTS != 0><<<grid, block, 0, s>>>(g, rpw, nrt, whole_rows, fin_n, omega);
+            copyback_kernel<VEC, NTL, NTS != 0, kRowUnroll>
+                <<<grid, block, 0, s>>>(g, rpw, nrt, whole_rows, fin_n, omega);
     }
 };
 
@@ -1295,16 +1301,22 @@ void launch_copyback(const GridView &g, int vec, int flags, hipStream_t s, bool 
                      float omega) {
     vec = std::min(vec, 4);  // p and wrk2 are FP32: 16 bytes per lane at 4 points
     const int nrt = itiles(g.I, vec) * (g.J - 2) * (g.K - 2);
-    // Each wave takes one round of 16 row tiles, all loads in flight before
-    // the first store. Per launch at 257x257x513: 39.5-39.6 us, against 42.6
-    // with two rounds of 4, 40.6 with two of 8, 43.4 with two of 16, 39.7 with
-    // one of 32 (which slows the batches); the 64-grid batches gain 0.3-1.7%.
-    // The residual keeps 4 per round: 40.7 us, 41.5 with 8.
-    const int blocks = grid_for(nrt, (kResidualThreads / kWave) * kCopyUnroll, kResidualBlocks * 4);
+    // A launch with enough row tiles gives each wave one round of 16, all
+    // loads in flight before the first store. Per launch at 257x257x513:
+    // 39.5-39.6 us, against 42.6 with two rounds of 4, 40.6 with two of 8,
+    // 43.4 with two of 16, 39.7 with one of 32 (which slows the batches); the
+    // 64-grid batches gain 0.3-1.7%. Below 4096 such waves (16 per CU) the
+    // rounds would leave CUs idle, so smaller launches (a grid of 129 x 129 x
+    // 257, one plane of a region gene) keep two rounds of 4 per wave. The
+    // residual keeps 4 per round: 40.7 us, 41.5 with 8.
+    constexpr int kWavesPerBlock = kResidualThreads / kWave;
+    const bool wide = nrt / kCopyUnroll >= 4096;
+    const int per_wave = wide ? kCopyUnroll : 2 * kRowUnroll;
+    const int blocks = grid_for(nrt, kWavesPerBlock * per_wave, kResidualBlocks * 4);
     const int rpw = rows_per_wave(nrt, blocks);
     by_vec_sum_nt<CopybackLaunch>(vec, (flags & OFL_TILE_NT_STORES) ? 1 : 0, (flags & OFL_TILE_NT_LOADS) != 0,
                                   dim3(blocks), dim3(kResidualThreads), s, g, rpw, nrt, whole_rows ? 1 : 0,
-                                  finalize_residual ? kResidualBlocks : 0, static_cast<double>(omega));
+                                  finalize_residual ? kResidualBlocks : 0, static_cast<double>(omega), wide);
     check_launch("copy-back kernel launch");
 }
 
