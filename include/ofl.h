@@ -257,7 +257,9 @@ int ofl_grid_coef_bias(const ofl_grid *g, float bias[12]);
                                  (copy-back) and of a batch residual's inputs; a single grid's
                                  residual always loads ordinarily, leaving p and wrk2 cached
                                  for the copy-back that follows */
-#define OFL_TILE_NT_STORES 2  /* non-temporal stores of wrk2 (sweep) and p (copy-back) */
+#define OFL_TILE_NT_STORES 2  /* non-temporal stores of wrk2 (sweep) and p (copy-back); a single
+                                 grid whose p takes 48 to 224 MiB stores p ordinarily in the
+                                 copy-back, so that the next sweep finds it in the last-level cache */
 #define OFL_TILE_PREFETCH 4   /* software-pipelined coefficient loads (next step during this one) */
 #define OFL_TILE_MARCH_J 8    /* waves march along j (own a k-plane) instead of along k (own a j-row) */
 #define OFL_TILE_XCD_REMAP 16 /* give each XCD one contiguous range of the sweep's tiles over the

@@ -322,6 +322,23 @@ const char *const kXferRange[2][14] = {
     {"ofl:d2h a0", "ofl:d2h a1", "ofl:d2h a2", "ofl:d2h a3", "ofl:d2h b0", "ofl:d2h b1", "ofl:d2h b2", "ofl:d2h c0",
      "ofl:d2h c1", "ofl:d2h c2", "ofl:d2h bnd", "ofl:d2h wrk1", "ofl:d2h p", "ofl:d2h wrk2"}};
 
+// Store kind of a single grid's copy-back. The sweep that follows reads every
+// plane of p again; when p fits in the last-level cache (256 MB on MI355X) with
+// room to spare, ordinary stores leave it there and that sweep reads it from
+// the cache, so the copy-back then ignores OFL_TILE_NT_STORES. Measured with
+// FP32 coefficients (whole steps, GLUP/s, non-temporal -> ordinary stores; p's
+// pitched bytes): 21 MB 62.9 -> 62.0, 67 MB 77.2 -> 78.7, 76 MB 82.8 -> 83.3,
+// 114 MB 84.1 -> 85.5, 144 MB 85.2 -> 86.0, 152 MB 84.8 -> 85.6, 213 MB 65.7 ->
+// 67.7, 290 MB 68.7 -> 67.5, 490 MB 71.9 -> 70.7. (The 64-grid batch, whose p
+// arrays come to 0.5 GB, keeps the tile's stores.)
+int copyback_flags(const ofl_grid *g) {
+    constexpr size_t kMin = size_t{48} << 20, kMax = size_t{224} << 20;
+    const size_t p_bytes = g->lay.elems * sizeof(float);
+    if (p_bytes >= kMin && p_bytes <= kMax)
+        return g->tile.flags & ~OFL_TILE_NT_STORES;
+    return g->tile.flags;
+}
+
 void gpu_nest(ofl_grid *g, int nest, float omega, bool fold) {
     TraceRange range(kNestRange[nest]);
     prof_begin(g, nest);
@@ -331,7 +348,7 @@ void gpu_nest(ofl_grid *g, int nest, float omega, bool fold) {
         launch_residual(g->view, g->tile.vec, g->sum_mode, g->tile.flags, omega, g->stream, !fold);
         g->gosa_on_dev = true;
     } else {
-        launch_copyback(g->view, g->tile.vec, g->tile.flags, g->stream, g->wrk2_boundary_ok, fold, omega);
+        launch_copyback(g->view, g->tile.vec, copyback_flags(g), g->stream, g->wrk2_boundary_ok, fold, omega);
     }
     prof_end(g);
     g->stats.gpu_nests[nest] += 1;
@@ -461,7 +478,7 @@ void gpu_nest_regions(ofl_grid *g, int nest, float omega, bool per_iter, const s
                                              hipMemcpyDeviceToHost, g->stream),
                               "hipMemcpyAsync(region sum)");
             } else {
-                launch_copyback(v, g->tile.vec, g->tile.flags, g->stream);
+                launch_copyback(v, g->tile.vec, copyback_flags(g), g->stream);
             }
             g->stats.gpu_regions[nest] += 1;
             g->pending = true;
@@ -587,7 +604,7 @@ void run_fused(ofl_grid *g, int iters, float omega, double *static_parts = nullp
             grid_swap_p_wrk2(g);
         } else {
             prof_begin(g, kC);
-            launch_copyback(g->view, g->tile.vec, g->tile.flags, g->stream, g->wrk2_boundary_ok);
+            launch_copyback(g->view, g->tile.vec, copyback_flags(g), g->stream, g->wrk2_boundary_ok);
             prof_end(g);
         }
         plan_after(it, kC, true, OFL_XFER_HOISTED, g->valid, xs);
@@ -643,7 +660,7 @@ void enqueue_iterations(ofl_grid *g, int iters, float omega) {
     for (int it = 0; it < iters; ++it) {
         launch_sweep(g->view, g->tile, g->fmt != OFL_COEF_F32, omega, g->stream);
         launch_residual(g->view, g->tile.vec, g->sum_mode, g->tile.flags, omega, g->stream, false);
-        launch_copyback(g->view, g->tile.vec, g->tile.flags, g->stream, g->wrk2_boundary_ok, true, omega);
+        launch_copyback(g->view, g->tile.vec, copyback_flags(g), g->stream, g->wrk2_boundary_ok, true, omega);
     }
 }
 
